@@ -1,0 +1,188 @@
+/*
+ * aco.h -- C ABI of libaco, an Ant System (AS) solver for the symmetric
+ * Euclidean TSP on AMD Instinct MI355X (gfx950).
+ *
+ * The library runs the two stages of an AS iteration on the GPU, following
+ * Cecilia et al., "Parallelization Strategies for Ant Colony Optimisation on
+ * GPUs" (arXiv:1101.2678):
+ *   - tour construction (Section II, Eq. 1; GPU design in Section III-A): one
+ *     workgroup per ant, cities spread over the lanes, next city drawn by
+ *     proportional roulette over choice = tau^alpha * eta^beta (eta = 1/d)
+ *     restricted to unvisited cities;
+ *   - pheromone update (Section II, Eqs. 2-4; GPU designs in Section III-B):
+ *     evaporation tau <- (1 - rho) tau, then every ant k deposits 1/C^k on
+ *     each edge of its tour, in either a scatter-to-gather (row owner) or an
+ *     atomic-deposit variant; the choice matrix is refreshed in the same pass.
+ *
+ * Conventions for every entry point:
+ *   - Nothing throws or aborts across the ABI; every call returns aco_status.
+ *   - "host" pointers are ordinary CPU memory, borrowed for the duration of
+ *     the call only.  "device" pointers are GPU memory owned by the caller.
+ *   - Work is enqueued on the caller's HIP stream (passed as void*, a
+ *     hipStream_t; NULL is the default stream).  Calls documented as
+ *     asynchronous return before the GPU finishes; the synchronous ones wait
+ *     on that stream.  A device error is reported as ACO_ERR_DEVICE by the
+ *     call that observes it, after which the context is poisoned and every
+ *     later call on it returns ACO_ERR_STATE.
+ *   - A context is not thread-safe.  Distinct contexts may run concurrently
+ *     on distinct streams.
+ *
+ * Arithmetic (identical on every path, and bit-exact against the oracle):
+ *   - random numbers: Philox4x32-10 with key = seed and counter
+ *     (step, ant, iter, 0); word 0 gives the start city ((x0*n) >> 32) at
+ *     step 0 and u = (x0 >> 8) * 2^-24 at step s >= 1;
+ *   - roulette ("R64"): feasible weights w_j = choice[i][j], blocks of 64
+ *     cities scanned by a fixed FP32 prefix tree, block totals scanned by the
+ *     same tree; the next city is the lowest feasible j whose prefix exceeds
+ *     fl32(u * total), else the highest feasible city;
+ *   - heur = fl32(1 / d^beta) (binary64 power and quotient), choice =
+ *     fl32(tau^alpha * heur), zero on the diagonal;
+ *   - update: tau <- fl32((double)fl32(tau * fl32(1 - rho)) + D) where D is the
+ *     binary64 sum of fl32(1 / C^k) over the ants using the edge (exact, so
+ *     independent of summation order);
+ *   - tau0 = fl32(m / C_nn), C_nn the nearest-neighbour tour length from
+ *     city 0 (ties to the lowest index).
+ */
+#ifndef ACO_H
+#define ACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ACO_OK = 0,
+    ACO_ERR_INVALID = 1, /* bad argument; nothing was enqueued */
+    ACO_ERR_NOMEM = 2,   /* workspace too small or misaligned */
+    ACO_ERR_DEVICE = 3,  /* a HIP call or kernel failed; context poisoned */
+    ACO_ERR_STATE = 4    /* call out of order, or context poisoned */
+} aco_status;
+
+typedef enum {
+    ACO_UPDATE_GATHER = 0, /* scatter-to-gather: one workgroup owns a row */
+    ACO_UPDATE_ATOMIC = 1  /* one thread per tour edge, binary64 atomics */
+} aco_update_kind;
+
+/* Problem and AS parameters.
+ *   n      number of cities, 3 <= n <= 4096
+ *   m      number of ants, 1 <= m <= 65535 (the paper uses m = n)
+ *   alpha  pheromone exponent, 0, 1 or 2
+ *   beta   heuristic exponent, 0 <= beta <= 4
+ *   rho    evaporation rate, 0 < rho <= 1 (Eq. 2)
+ *   seed   Philox key */
+typedef struct {
+    int32_t n;
+    int32_t m;
+    int32_t alpha;
+    int32_t beta;
+    float rho;
+    uint64_t seed;
+} aco_params;
+
+typedef struct aco_ctx aco_ctx; /* opaque; host memory owned by the library */
+
+/* Exact number of device bytes aco_init needs for these parameters.
+ * with_atomic != 0 also reserves the binary64 deposit matrix that
+ * ACO_UPDATE_ATOMIC uses (8 * n * ld bytes, ld = n rounded up to 64).
+ * Returns 0 if the parameters are invalid. */
+size_t aco_workspace_bytes(const aco_params* p, int32_t with_atomic);
+
+/* Create a context on the current HIP device.
+ *   out          receives the context (host)
+ *   p            parameters (host)
+ *   dist_host    n*n int32 row-major distances (host, borrowed for the call);
+ *                must be symmetric with a zero diagonal and d_ij >= 1 off it
+ *   d_workspace  device buffer of ws_bytes >= aco_workspace_bytes(p, 0),
+ *                256-byte aligned, owned by the caller and never freed by the
+ *                library; it holds tau, choice, distances, tours and all
+ *                per-iteration state.  If ws_bytes also covers the atomic
+ *                size, ACO_UPDATE_ATOMIC is available.
+ *   hip_stream   the stream every later call of this context enqueues on
+ * Uploads the distances, computes C_nn and tau0 on the GPU, fills tau and
+ * choice.  Synchronous.  Errors: ACO_ERR_INVALID (parameters, distances),
+ * ACO_ERR_NOMEM (workspace), ACO_ERR_DEVICE. */
+aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host,
+                    void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Tour construction for iteration `iter` (Section II, Eq. 1): all m ants
+ * build a tour from the current choice matrix; writes tours, lengths C^k,
+ * deposits fl32(1/C^k) and the best-so-far tour.  Asynchronous. */
+aco_status aco_construct(aco_ctx* c, uint32_t iter);
+
+/* Pheromone update (Eqs. 2-4) from the tours of the last aco_construct, then
+ * choice refresh.  Asynchronous.  ACO_ERR_STATE if no construction preceded
+ * it since the last update; ACO_ERR_INVALID for ACO_UPDATE_ATOMIC without the
+ * atomic workspace. */
+aco_status aco_update(aco_ctx* c, aco_update_kind kind);
+
+/* Runs `iters` iterations (construct, update) starting at the context's
+ * iteration counter, then copies the best-so-far tour (n+1 uint16, host) and
+ * its length (host) out.  Synchronous.  Either output pointer may be NULL. */
+aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                     uint16_t* best_tour_host, int64_t* best_len_host);
+
+/* Copies of the device state into host memory.  Synchronous.
+ *   tours: m*(n+1) uint16 of the last construction; lens: m int64 (either may
+ *   be NULL); tau, choice: n*n float row-major; best_tour: n+1 uint16. */
+aco_status aco_read_tours(aco_ctx* c, uint16_t* tours_host, int64_t* lens_host);
+aco_status aco_read_tau(aco_ctx* c, float* tau_host);
+aco_status aco_read_choice(aco_ctx* c, float* choice_host);
+aco_status aco_read_best(aco_ctx* c, uint16_t* best_tour_host, int64_t* best_len_host);
+
+/* Checkpoint restore: replaces tau with the host copy (n*n row-major, e.g.
+ * from aco_read_tau), recomputes choice, and sets the iteration counter and
+ * best-so-far length (best tour cleared if best_len < 0).  Because every
+ * random number is keyed by (seed, iter, ant, step), a resumed run
+ * reproduces the uninterrupted one.  Synchronous. */
+aco_status aco_restore(aco_ctx* c, const float* tau_host, uint32_t iter, int64_t best_len,
+                       const uint16_t* best_tour_host);
+
+/* Iteration counter used by aco_solve (the next iteration to run). */
+aco_status aco_get_iter(aco_ctx* c, uint32_t* iter);
+
+/* Waits for all work of this context's stream. */
+aco_status aco_sync(aco_ctx* c);
+
+/* Frees the host context.  Never touches the workspace. */
+void aco_destroy(aco_ctx* c);
+
+const char* aco_status_str(aco_status s);
+
+/* Human-readable detail of the last failure on this thread ("" if none). */
+const char* aco_last_error(void);
+
+/* Kernel configuration chosen for a context, as "key=value" pairs. */
+aco_status aco_describe(aco_ctx* c, char* buf, size_t len);
+
+/* ---- verification and measurement entry points ------------------------ */
+
+/* R64 roulette on `count` independent rows through the same device code the
+ * construction kernel uses (Section II, Eq. 1).
+ *   rows_dev      count rows of `ld` floats (device), ld = n rounded up to
+ *                 64; columns n..ld-1 must be zero
+ *   feasible_dev  count*n uint8 (device), non-zero = city may be chosen
+ *   u_dev         count floats in [0, 1) (device)
+ *   out_dev       count int32 (device): the chosen city, -1 if none feasible
+ * Asynchronous on hip_stream. */
+aco_status aco_test_select(int32_t n, int32_t count, const float* rows_dev,
+                           const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
+                           void* hip_stream);
+
+/* Streams `bytes` (multiple of 16) from src_dev to dst_dev with 16-byte loads
+ * and stores: a plain copy kernel of known traffic, used to calibrate
+ * hardware byte counters and to measure achievable bandwidth.  Async. */
+aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
+
+/* Reads `bytes` (multiple of 16) of src_dev `reps` times and writes one
+ * float per workgroup to sink_dev (>= 4096 floats): read bandwidth at a
+ * footprint that fits or does not fit the on-die caches.  Async. */
+aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
+                          void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACO_H */

@@ -74,6 +74,8 @@ def lib():
         L.oracle_s64.restype = None
         L.oracle_r64_select.argtypes = [c.c_int32, _f32p, _u8p, c.c_float]
         L.oracle_r64_select.restype = c.c_int32
+        L.oracle_r64_select_batch.argtypes = [c.c_int32, c.c_int32, _f32p, _u8p, _f32p, _i32p]
+        L.oracle_r64_select_batch.restype = None
         L.oracle_construct_ant.argtypes = [c.c_int32, _f32p, _i32p, c.c_uint64, c.c_uint32,
                                            c.c_uint32, _u16p]
         L.oracle_construct_ant.restype = c.c_int64
@@ -138,6 +140,15 @@ def r64_select(row, feasible, u: float) -> int:
     row = np.ascontiguousarray(row, np.float32)
     feas = np.ascontiguousarray(feasible, np.uint8)
     return int(lib().oracle_r64_select(row.shape[0], row, feas, np.float32(u)))
+
+
+def r64_select_batch(rows, feasible, u) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, np.float32)
+    count, n = rows.shape
+    out = np.empty(count, np.int32)
+    lib().oracle_r64_select_batch(n, count, rows, np.ascontiguousarray(feasible, np.uint8),
+                                  np.ascontiguousarray(u, np.float32), out)
+    return out
 
 
 def construct_ant(choice_m: np.ndarray, dist: np.ndarray, seed: int, it: int, ant: int):

@@ -192,6 +192,12 @@ int32_t oracle_r64_select(int32_t n, const float* row, const uint8_t* feasible, 
     return pick;
 }
 
+void oracle_r64_select_batch(int32_t n, int32_t count, const float* rows,
+                             const uint8_t* feasible, const float* u, int32_t* out) {
+    for (int32_t q = 0; q < count; ++q)
+        out[q] = oracle_r64_select(n, rows + (int64_t)q * n, feasible + (int64_t)q * n, u[q]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Tour construction (Section II, random proportional rule).                 */
 /* ------------------------------------------------------------------------ */

@@ -91,6 +91,11 @@ void oracle_s64(const float in[64], float out[64]);
  * Returns j*, or -1 if no city is feasible.  n <= 4096. */
 int32_t oracle_r64_select(int32_t n, const float* row, const uint8_t* feasible, float u);
 
+/* oracle_r64_select on `count` rows (row q at rows + q*n, feasibility at
+ * feasible + q*n), one after the other. */
+void oracle_r64_select_batch(int32_t n, int32_t count, const float* rows,
+                             const uint8_t* feasible, const float* u, int32_t* out);
+
 /* One ant's tour (Section II): placement, then n-1 roulette steps over the
  * choice row of the current city with the visited cities masked out.
  * tour gets n+1 entries; returns the tour length C^k (int64). */

@@ -1,0 +1,225 @@
+"""ctypes binding of libaco (include/aco.h).
+
+Argument marshalling only: every step of the Ant System runs in the HIP
+kernels of libaco.so.  torch provides the device workspace and the stream.
+If libaco.so is missing, importing this module raises; nothing falls back to
+a CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaco.so")
+
+ACO_OK, ACO_ERR_INVALID, ACO_ERR_NOMEM, ACO_ERR_DEVICE, ACO_ERR_STATE = range(5)
+GATHER, ATOMIC = 0, 1
+_KIND = {"gather": GATHER, "atomic": ATOMIC, GATHER: GATHER, ATOMIC: ATOMIC}
+
+
+class AcoError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("alpha", ctypes.c_int32),
+                ("beta", ctypes.c_int32), ("rho", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1101_2678_amd._build` "
+            "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    vp, sz, i32, u32, i64 = c.c_void_p, c.c_size_t, c.c_int32, c.c_uint32, c.c_int64
+    sigs = {
+        "aco_workspace_bytes": (sz, [c.POINTER(Params), i32]),
+        "aco_init": (i32, [c.POINTER(vp), c.POINTER(Params), vp, vp, sz, vp]),
+        "aco_construct": (i32, [vp, u32]),
+        "aco_update": (i32, [vp, i32]),
+        "aco_solve": (i32, [vp, u32, i32, vp, vp]),
+        "aco_read_tours": (i32, [vp, vp, vp]),
+        "aco_read_tau": (i32, [vp, vp]),
+        "aco_read_choice": (i32, [vp, vp]),
+        "aco_read_best": (i32, [vp, vp, vp]),
+        "aco_restore": (i32, [vp, vp, u32, i64, vp]),
+        "aco_get_iter": (i32, [vp, c.POINTER(u32)]),
+        "aco_sync": (i32, [vp]),
+        "aco_destroy": (None, [vp]),
+        "aco_status_str": (c.c_char_p, [i32]),
+        "aco_last_error": (c.c_char_p, []),
+        "aco_describe": (i32, [vp, c.c_char_p, sz]),
+        "aco_test_select": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+        "aco_probe_copy": (i32, [vp, vp, sz, vp]),
+        "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int, where: str):
+    if status != ACO_OK:
+        detail = (lib.aco_last_error() or b"").decode() or lib.aco_status_str(status).decode()
+        raise AcoError(status, where, detail)
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_bytes(n: int, m: int, alpha: int = 1, beta: int = 2, rho: float = 0.5,
+                    seed: int = 1, atomic: bool = True) -> int:
+    p = Params(n, m, alpha, beta, rho, seed)
+    return int(lib.aco_workspace_bytes(ctypes.byref(p), 1 if atomic else 0))
+
+
+class Colony:
+    """One Ant System instance resident on a GPU.
+
+    dist: (n, n) int32 symmetric distance matrix (host numpy array).
+    The device workspace is a torch uint8 tensor; all kernels run on `stream`
+    (default: torch's current stream on `device`).
+    """
+
+    def __init__(self, dist, m: int, alpha: int = 1, beta: int = 2, rho: float = 0.5,
+                 seed: int = 1, atomic: bool = True, device="cuda", stream=None):
+        import torch
+
+        d = np.ascontiguousarray(dist, dtype=np.int32)
+        if d.ndim != 2 or d.shape[0] != d.shape[1]:
+            raise ValueError("dist must be a square matrix")
+        self.n, self.m = int(d.shape[0]), int(m)
+        self.params = Params(self.n, self.m, alpha, beta, rho, seed)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.atomic = bool(atomic)
+        nbytes = lib.aco_workspace_bytes(ctypes.byref(self.params), 1 if atomic else 0)
+        if nbytes == 0:
+            _check(ACO_ERR_INVALID, "aco_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.aco_init(ctypes.byref(self._ctx), ctypes.byref(self.params),
+                                d.ctypes.data_as(ctypes.c_void_p),
+                                ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                _stream_handle(self.stream)), "aco_init")
+
+    # ---- asynchronous steps
+    def construct(self, it: int):
+        _check(lib.aco_construct(self._ctx, it), "aco_construct")
+
+    def update(self, kind="gather"):
+        _check(lib.aco_update(self._ctx, _KIND[kind]), "aco_update")
+
+    # ---- synchronous calls
+    def solve(self, iters: int, kind="gather"):
+        tour = np.empty(self.n + 1, np.uint16)
+        length = ctypes.c_int64()
+        _check(lib.aco_solve(self._ctx, iters, _KIND[kind], tour.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(length)), "aco_solve")
+        return tour, int(length.value)
+
+    def tours(self):
+        t = np.empty((self.m, self.n + 1), np.uint16)
+        ln = np.empty(self.m, np.int64)
+        _check(lib.aco_read_tours(self._ctx, t.ctypes.data_as(ctypes.c_void_p),
+                                  ln.ctypes.data_as(ctypes.c_void_p)), "aco_read_tours")
+        return t, ln
+
+    def tau(self):
+        out = np.empty((self.n, self.n), np.float32)
+        _check(lib.aco_read_tau(self._ctx, out.ctypes.data_as(ctypes.c_void_p)), "aco_read_tau")
+        return out
+
+    def choice(self):
+        out = np.empty((self.n, self.n), np.float32)
+        _check(lib.aco_read_choice(self._ctx, out.ctypes.data_as(ctypes.c_void_p)),
+               "aco_read_choice")
+        return out
+
+    def best(self):
+        tour = np.empty(self.n + 1, np.uint16)
+        length = ctypes.c_int64()
+        _check(lib.aco_read_best(self._ctx, tour.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(length)), "aco_read_best")
+        return tour, int(length.value)
+
+    def restore(self, tau, it: int, best_len: int = -1, best_tour=None):
+        t = np.ascontiguousarray(tau, np.float32)
+        bt = None if best_tour is None else np.ascontiguousarray(best_tour, np.uint16)
+        _check(lib.aco_restore(self._ctx, t.ctypes.data_as(ctypes.c_void_p), it, best_len,
+                               None if bt is None else bt.ctypes.data_as(ctypes.c_void_p)),
+               "aco_restore")
+
+    @property
+    def iteration(self) -> int:
+        v = ctypes.c_uint32()
+        _check(lib.aco_get_iter(self._ctx, ctypes.byref(v)), "aco_get_iter")
+        return int(v.value)
+
+    def sync(self):
+        _check(lib.aco_sync(self._ctx), "aco_sync")
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(lib.aco_describe(self._ctx, buf, 512), "aco_describe")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib.aco_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def test_select(rows, feasible, u, stream=None):
+    """R64 roulette on independent rows through the construction kernel's code.
+    rows: (count, n) float32 torch tensor on the GPU; feasible: (count, n)
+    uint8; u: (count,) float32.  Returns a (count,) int32 tensor."""
+    import torch
+
+    count, n = rows.shape
+    ld = (n + 63) // 64 * 64
+    padded = torch.zeros((count, ld), dtype=torch.float32, device=rows.device)
+    padded[:, :n] = rows
+    feas = feasible.to(torch.uint8).contiguous()
+    uu = u.to(torch.float32).contiguous()
+    out = torch.empty(count, dtype=torch.int32, device=rows.device)
+    _check(lib.aco_test_select(n, count, ctypes.c_void_p(padded.data_ptr()),
+                               ctypes.c_void_p(feas.data_ptr()), ctypes.c_void_p(uu.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "aco_test_select")
+    return out
+
+
+def probe_copy(dst, src, stream=None):
+    _check(lib.aco_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                              src.numel() * src.element_size(), _stream_handle(stream)),
+           "aco_probe_copy")
+
+
+def probe_read(src, reps: int, sink, stream=None):
+    _check(lib.aco_probe_read(ctypes.c_void_p(src.data_ptr()), src.numel() * src.element_size(),
+                              reps, ctypes.c_void_p(sink.data_ptr()), _stream_handle(stream)),
+           "aco_probe_read")

@@ -1,0 +1,399 @@
+// aco_abi.hip -- the C ABI of libaco (declared in include/aco.h): argument
+// validation, workspace carving, the per-context state machine and error
+// reporting.  All arithmetic of the method runs in the kernels of
+// construct.hip and update.hip; this file only moves bytes and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "aco.h"
+#include "aco_state.hpp"
+
+struct aco_ctx {
+    aco::Colony col;
+    hipStream_t stream;
+    size_t ws_bytes;
+    uint32_t next_iter;     // first iteration aco_solve runs
+    uint32_t pending_iter;  // iteration of the construction awaiting update
+    bool pending;           // a construction has not been followed by an update
+    bool poisoned;
+    bool has_atomic;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+aco_status fail(aco_status s, const std::string& why) {
+    g_error = why;
+    return s;
+}
+
+aco_status device_fail(aco_ctx* c, hipError_t e, const char* where) {
+    if (c) c->poisoned = true;
+    return fail(ACO_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool params_valid(const aco_params* p, std::string* why) {
+    if (!p) return (*why = "params is NULL", false);
+    if (p->n < 3 || p->n > aco::kMaxCities) return (*why = "n must be in [3, 4096]", false);
+    if (p->m < 1 || p->m > 65535) return (*why = "m must be in [1, 65535]", false);
+    if (p->alpha < 0 || p->alpha > 2) return (*why = "alpha must be 0, 1 or 2", false);
+    if (p->beta < 0 || p->beta > 4) return (*why = "beta must be in [0, 4]", false);
+    if (!(p->rho > 0.0f && p->rho <= 1.0f)) return (*why = "rho must be in (0, 1]", false);
+    return true;
+}
+
+// Byte offsets of every array inside the workspace.
+struct Layout {
+    int32_t ld, tp, mp;
+    size_t tau, choice, dist, tours, succ, pred, lens, dep, best_len, best_tour, cnn, tau0,
+        delta, base_end, atomic_end;
+};
+
+Layout make_layout(const aco_params& p) {
+    Layout L{};
+    L.ld = (int32_t)round_up((size_t)p.n, 64);
+    L.tp = (int32_t)round_up((size_t)p.n + 1, 64);
+    L.mp = (int32_t)round_up((size_t)p.m, 64);
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off = round_up(off + bytes, kAlign);
+        return o;
+    };
+    const size_t cells = (size_t)p.n * L.ld;
+    L.tau = take(cells * sizeof(float));
+    L.choice = take(cells * sizeof(float));
+    L.dist = take(cells * sizeof(int32_t));
+    L.tours = take((size_t)p.m * L.tp * sizeof(uint16_t));
+    L.succ = take((size_t)p.n * L.mp * sizeof(uint16_t));
+    L.pred = take((size_t)p.n * L.mp * sizeof(uint16_t));
+    L.lens = take((size_t)p.m * sizeof(int64_t));
+    L.dep = take((size_t)p.m * sizeof(float));
+    L.best_len = take(sizeof(int64_t));
+    L.best_tour = take((size_t)L.tp * sizeof(uint16_t));
+    L.cnn = take(sizeof(int64_t));
+    L.tau0 = take(sizeof(float));
+    L.base_end = off;
+    L.delta = take(cells * sizeof(double));
+    L.atomic_end = off;
+    return L;
+}
+
+// Distances must describe a symmetric complete graph (Section II) with
+// positive off-diagonal weights.  The deposit sums of the update are exact
+// in binary64 only if the deposits 1/C^k span few binades: with
+// LB <= C^k <= UB (each city contributes half of its two cheapest / two
+// dearest incident edges) we need bits(m) + bits(UB/LB) + 1 + 24 <= 53.
+bool dist_valid(const int32_t* d, int n, int m, std::string* why) {
+    double lb = 0.0, ub = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (d[(size_t)i * n + i] != 0) return (*why = "distance matrix diagonal must be 0", false);
+        int64_t lo1 = INT64_MAX, lo2 = INT64_MAX, hi1 = -1, hi2 = -1;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const int32_t v = d[(size_t)i * n + j];
+            if (v < 1) return (*why = "off-diagonal distances must be >= 1", false);
+            if (v != d[(size_t)j * n + i]) return (*why = "distance matrix must be symmetric", false);
+            if (v < lo1) { lo2 = lo1; lo1 = v; } else if (v < lo2) lo2 = v;
+            if (v > hi1) { hi2 = hi1; hi1 = v; } else if (v > hi2) hi2 = v;
+        }
+        lb += 0.5 * (double)(lo1 + lo2);
+        ub += 0.5 * (double)(hi1 + hi2);
+    }
+    int mbits = 0;
+    while ((1LL << mbits) < (long long)m) ++mbits;
+    const int spread = (int)std::ceil(std::log2(ub / lb)) + 1;
+    if (mbits + spread + 24 > 53)
+        return (*why = "tour lengths span too many binades for exact binary64 deposit sums", false);
+    return true;
+}
+
+aco_status usable(aco_ctx* c) {
+    if (!c) return fail(ACO_ERR_INVALID, "context is NULL");
+    if (c->poisoned) return fail(ACO_ERR_STATE, "context poisoned by an earlier device error");
+    return ACO_OK;
+}
+
+aco_status sync_ctx(aco_ctx* c, const char* where) {
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, where);
+    return ACO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aco_status_str(aco_status s) {
+    switch (s) {
+        case ACO_OK: return "ok";
+        case ACO_ERR_INVALID: return "invalid argument";
+        case ACO_ERR_NOMEM: return "workspace too small or misaligned";
+        case ACO_ERR_DEVICE: return "device error";
+        case ACO_ERR_STATE: return "invalid call order or poisoned context";
+    }
+    return "unknown status";
+}
+
+const char* aco_last_error(void) { return g_error.c_str(); }
+
+size_t aco_workspace_bytes(const aco_params* p, int32_t with_atomic) {
+    std::string why;
+    if (!params_valid(p, &why)) return 0;
+    const Layout L = make_layout(*p);
+    return with_atomic ? L.atomic_end : L.base_end;
+}
+
+aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host,
+                    void* d_workspace, size_t ws_bytes, void* hip_stream) {
+    g_error.clear();
+    if (!out) return fail(ACO_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!params_valid(p, &why)) return fail(ACO_ERR_INVALID, why);
+    if (!dist_host) return fail(ACO_ERR_INVALID, "dist_host is NULL");
+    if (!dist_valid(dist_host, p->n, p->m, &why)) return fail(ACO_ERR_INVALID, why);
+    const Layout L = make_layout(*p);
+    if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+        return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < L.base_end)
+        return fail(ACO_ERR_NOMEM, "workspace smaller than aco_workspace_bytes(p, 0)");
+
+    aco_ctx* c = new (std::nothrow) aco_ctx();
+    if (!c) return fail(ACO_ERR_NOMEM, "host allocation failed");
+    char* base = static_cast<char*>(d_workspace);
+    aco::Colony& col = c->col;
+    col.n = p->n;
+    col.m = p->m;
+    col.ld = L.ld;
+    col.tp = L.tp;
+    col.mp = L.mp;
+    col.alpha = p->alpha;
+    col.beta = p->beta;
+    col.rho = p->rho;
+    col.seed = p->seed;
+    col.tau = reinterpret_cast<float*>(base + L.tau);
+    col.choice = reinterpret_cast<float*>(base + L.choice);
+    col.dist = reinterpret_cast<int32_t*>(base + L.dist);
+    col.tours = reinterpret_cast<uint16_t*>(base + L.tours);
+    col.succ = reinterpret_cast<uint16_t*>(base + L.succ);
+    col.pred = reinterpret_cast<uint16_t*>(base + L.pred);
+    col.lens = reinterpret_cast<int64_t*>(base + L.lens);
+    col.dep = reinterpret_cast<float*>(base + L.dep);
+    col.best_len = reinterpret_cast<int64_t*>(base + L.best_len);
+    col.best_tour = reinterpret_cast<uint16_t*>(base + L.best_tour);
+    col.cnn = reinterpret_cast<int64_t*>(base + L.cnn);
+    col.tau0 = reinterpret_cast<float*>(base + L.tau0);
+    c->has_atomic = ws_bytes >= L.atomic_end;
+    col.delta = c->has_atomic ? reinterpret_cast<double*>(base + L.delta) : nullptr;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws_bytes = ws_bytes;
+
+    hipError_t e = hipMemsetAsync(base, 0, L.base_end, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(col.dist, (size_t)L.ld * sizeof(int32_t), dist_host,
+                             (size_t)p->n * sizeof(int32_t), (size_t)p->n * sizeof(int32_t),
+                             (size_t)p->n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = aco::launch_init(col, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        aco_status s = device_fail(c, e, "aco_init");
+        delete c;
+        return s;
+    }
+    *out = c;
+    return ACO_OK;
+}
+
+aco_status aco_construct(aco_ctx* c, uint32_t iter) {
+    if (aco_status s = usable(c)) return s;
+    hipError_t e = aco::launch_construct(c->col, iter, c->stream);
+    if (e == hipSuccess) e = aco::launch_best(c->col, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "aco_construct");
+    c->pending = true;
+    c->pending_iter = iter;
+    return ACO_OK;
+}
+
+aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
+    if (aco_status s = usable(c)) return s;
+    if (!c->pending) return fail(ACO_ERR_STATE, "aco_update needs a preceding aco_construct");
+    hipError_t e;
+    if (kind == ACO_UPDATE_GATHER) {
+        e = aco::launch_update_gather(c->col, c->stream);
+    } else if (kind == ACO_UPDATE_ATOMIC) {
+        if (!c->has_atomic)
+            return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
+        e = aco::launch_update_atomic(c->col, c->stream);
+    } else {
+        return fail(ACO_ERR_INVALID, "unknown update kind");
+    }
+    if (e != hipSuccess) return device_fail(c, e, "aco_update");
+    c->pending = false;
+    c->next_iter = c->pending_iter + 1;
+    return ACO_OK;
+}
+
+aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind, uint16_t* best_tour_host,
+                     int64_t* best_len_host) {
+    if (aco_status s = usable(c)) return s;
+    if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
+        return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
+    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
+        return fail(ACO_ERR_INVALID, "unknown update kind");
+    for (uint32_t i = 0; i < iters; ++i) {
+        if (aco_status s = aco_construct(c, c->next_iter)) return s;
+        if (aco_status s = aco_update(c, kind)) return s;
+    }
+    return aco_read_best(c, best_tour_host, best_len_host);
+}
+
+aco_status aco_read_best(aco_ctx* c, uint16_t* best_tour_host, int64_t* best_len_host) {
+    if (aco_status s = usable(c)) return s;
+    if (aco_status s = sync_ctx(c, "aco_read_best")) return s;
+    hipError_t e = hipSuccess;
+    if (best_len_host)
+        e = hipMemcpy(best_len_host, c->col.best_len, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && best_tour_host)
+        e = hipMemcpy(best_tour_host, c->col.best_tour, ((size_t)c->col.n + 1) * sizeof(uint16_t),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(c, e, "aco_read_best");
+    return ACO_OK;
+}
+
+aco_status aco_read_tours(aco_ctx* c, uint16_t* tours_host, int64_t* lens_host) {
+    if (aco_status s = usable(c)) return s;
+    if (aco_status s = sync_ctx(c, "aco_read_tours")) return s;
+    const aco::Colony& col = c->col;
+    hipError_t e = hipSuccess;
+    if (tours_host)
+        e = hipMemcpy2D(tours_host, ((size_t)col.n + 1) * sizeof(uint16_t), col.tours,
+                        (size_t)col.tp * sizeof(uint16_t), ((size_t)col.n + 1) * sizeof(uint16_t),
+                        (size_t)col.m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && lens_host)
+        e = hipMemcpy(lens_host, col.lens, (size_t)col.m * sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(c, e, "aco_read_tours");
+    return ACO_OK;
+}
+
+static aco_status read_matrix(aco_ctx* c, const float* src, float* host, const char* where) {
+    if (aco_status s = usable(c)) return s;
+    if (!host) return fail(ACO_ERR_INVALID, "host pointer is NULL");
+    if (aco_status s = sync_ctx(c, where)) return s;
+    const aco::Colony& col = c->col;
+    const hipError_t e = hipMemcpy2D(host, (size_t)col.n * sizeof(float), src,
+                                     (size_t)col.ld * sizeof(float), (size_t)col.n * sizeof(float),
+                                     (size_t)col.n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(c, e, where);
+    return ACO_OK;
+}
+
+aco_status aco_read_tau(aco_ctx* c, float* tau_host) {
+    return read_matrix(c, c ? c->col.tau : nullptr, tau_host, "aco_read_tau");
+}
+
+aco_status aco_read_choice(aco_ctx* c, float* choice_host) {
+    return read_matrix(c, c ? c->col.choice : nullptr, choice_host, "aco_read_choice");
+}
+
+aco_status aco_restore(aco_ctx* c, const float* tau_host, uint32_t iter, int64_t best_len,
+                       const uint16_t* best_tour_host) {
+    if (aco_status s = usable(c)) return s;
+    if (!tau_host) return fail(ACO_ERR_INVALID, "tau_host is NULL");
+    if (aco_status s = sync_ctx(c, "aco_restore")) return s;
+    const aco::Colony& col = c->col;
+    for (size_t i = 0; i < (size_t)col.n * col.n; ++i)
+        if (!(tau_host[i] >= 0.0f) || std::isinf(tau_host[i]))
+            return fail(ACO_ERR_INVALID, "tau must be finite and non-negative");
+    hipError_t e = hipMemcpy2D(col.tau, (size_t)col.ld * sizeof(float), tau_host,
+                               (size_t)col.n * sizeof(float), (size_t)col.n * sizeof(float),
+                               (size_t)col.n, hipMemcpyHostToDevice);
+    const int64_t bl = best_len < 0 ? INT64_MAX : best_len;
+    if (e == hipSuccess)
+        e = hipMemcpy(col.best_len, &bl, sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && best_tour_host && best_len >= 0)
+        e = hipMemcpy(col.best_tour, best_tour_host, ((size_t)col.n + 1) * sizeof(uint16_t),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = aco::launch_refresh_choice(col, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "aco_restore");
+    c->next_iter = iter;
+    c->pending = false;
+    return ACO_OK;
+}
+
+aco_status aco_get_iter(aco_ctx* c, uint32_t* iter) {
+    if (aco_status s = usable(c)) return s;
+    if (!iter) return fail(ACO_ERR_INVALID, "iter is NULL");
+    *iter = c->next_iter;
+    return ACO_OK;
+}
+
+aco_status aco_sync(aco_ctx* c) {
+    if (aco_status s = usable(c)) return s;
+    return sync_ctx(c, "aco_sync");
+}
+
+void aco_destroy(aco_ctx* c) { delete c; }
+
+aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
+    if (!c) return fail(ACO_ERR_INVALID, "context is NULL");
+    if (!buf || len == 0) return fail(ACO_ERR_INVALID, "buffer is NULL");
+    const aco::Colony& col = c->col;
+    std::snprintf(buf, len,
+                  "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
+                  "update_gather_threads=256 atomic=%d",
+                  aco::kCitiesPerLane, (col.n + aco::kPassCities - 1) / aco::kPassCities,
+                  (col.n + 63) / 64, col.ld, c->has_atomic ? 1 : 0);
+    return ACO_OK;
+}
+
+aco_status aco_test_select(int32_t n, int32_t count, const float* rows_dev,
+                           const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
+                           void* hip_stream) {
+    if (n < 1 || n > aco::kMaxCities) return fail(ACO_ERR_INVALID, "n must be in [1, 4096]");
+    if (count < 0) return fail(ACO_ERR_INVALID, "count must be >= 0");
+    if (count > 0 && (!rows_dev || !feasible_dev || !u_dev || !out_dev))
+        return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)rows_dev % 16) != 0)
+        return fail(ACO_ERR_INVALID, "rows must be 16-byte aligned");
+    const hipError_t e = aco::launch_test_select(n, count, rows_dev, feasible_dev, u_dev, out_dev,
+                                                 static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_test_select");
+    return ACO_OK;
+}
+
+aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {
+    if (bytes % 16 != 0) return fail(ACO_ERR_INVALID, "bytes must be a multiple of 16");
+    if (bytes && (!dst_dev || !src_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)dst_dev | (uintptr_t)src_dev) % 16 != 0)
+        return fail(ACO_ERR_INVALID, "buffers must be 16-byte aligned");
+    const hipError_t e =
+        aco::launch_probe_copy(dst_dev, src_dev, bytes, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_copy");
+    return ACO_OK;
+}
+
+aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
+                          void* hip_stream) {
+    if (bytes % 16 != 0) return fail(ACO_ERR_INVALID, "bytes must be a multiple of 16");
+    if (reps < 0) return fail(ACO_ERR_INVALID, "reps must be >= 0");
+    if (bytes && (!src_dev || !sink_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)src_dev % 16) != 0) return fail(ACO_ERR_INVALID, "src must be 16-byte aligned");
+    const hipError_t e = aco::launch_probe_read(src_dev, bytes, reps, sink_dev,
+                                                static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_read");
+    return ACO_OK;
+}
+
+}  // extern "C"

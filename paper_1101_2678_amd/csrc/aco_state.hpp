@@ -1,0 +1,53 @@
+// aco_state.hpp -- device-side view of one colony and the launchers of the
+// libaco kernels.  Host code only ever passes this struct by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace aco {
+
+// One colony's arrays, carved out of the caller's workspace.
+//   ld  row pitch (elements) of tau, choice, dist, delta: n rounded up to 64
+//   tp  row pitch of tours: n+1 rounded up to 64
+//   mp  row pitch of succ/pred: m rounded up to 64
+struct Colony {
+    int32_t n, m, ld, tp, mp;
+    int32_t alpha, beta;
+    float rho;
+    uint64_t seed;
+    float* tau;          // n x ld, FP32 pheromone; padding columns stay 0
+    float* choice;       // n x ld, FP32 tau^alpha * eta^beta; padding 0
+    int32_t* dist;       // n x ld, int32 distances; padding 0
+    uint16_t* tours;     // m x tp, tour k in row k (n+1 entries)
+    uint16_t* succ;      // n x mp: succ[i][k] = city after i in tour k
+    uint16_t* pred;      // n x mp: pred[i][k] = city before i in tour k
+    int64_t* lens;       // m tour lengths C^k
+    float* dep;          // m deposits fl32(1 / C^k)
+    int64_t* best_len;   // best-so-far length
+    uint16_t* best_tour; // tp entries
+    int64_t* cnn;        // nearest-neighbour tour length
+    float* tau0;         // m / C_nn
+    double* delta;       // n x ld binary64 deposits (atomic update), or null
+};
+
+// Cities each lane handles per pass of the construction kernel, and the
+// number of cities one pass of a wavefront covers.
+constexpr int kCitiesPerLane = 8;
+constexpr int kPassCities = 64 * kCitiesPerLane;
+constexpr int kMaxCities = 4096;
+
+hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
+hipError_t launch_best(const Colony& c, hipStream_t s);
+hipError_t launch_update_gather(const Colony& c, hipStream_t s);
+hipError_t launch_update_atomic(const Colony& c, hipStream_t s);
+hipError_t launch_init(const Colony& c, hipStream_t s);
+hipError_t launch_refresh_choice(const Colony& c, hipStream_t s);
+hipError_t launch_test_select(int n, int count, const float* rows, const uint8_t* feasible,
+                              const float* u, int32_t* out, hipStream_t s);
+hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_probe_read(const void* src, size_t bytes, int reps, float* sink,
+                             hipStream_t s);
+
+}  // namespace aco

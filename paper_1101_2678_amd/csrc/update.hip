@@ -1,0 +1,269 @@
+// update.hip -- pheromone update (Section II, Eqs. 2-4; GPU designs in
+// Section III-B), initialisation and the best-so-far tour.
+//
+// Both update variants produce the same bits: the deposits reaching a cell
+// are binary32 values summed in binary64, and with at most m <= 2^16 terms
+// whose exponents span at most 12 binades (every tour length lies between
+// about 2 d_max and n d_max, n <= 4096) the sum needs fewer than 53 bits, so
+// it is exact in any order.  The evaporated value and that sum are then
+// added with a single rounding:  tau' = fl32((double)fl32(tau * keep) + D).
+//
+//   gather  (scatter-to-gather, Section III-B, without the O(n^4) scan): one
+//           workgroup owns row i, reads succ[i][*] and pred[i][*] (the two
+//           tour neighbours of city i in every ant's tour), accumulates the
+//           deposits in binary64 LDS slots, then evaporates, adds and
+//           refreshes the choice row.  No global atomics.
+//   atomic  (Section III-B, "a thread per city in an ant's tour"): each tour
+//           edge adds its deposit to both (i, j) and (j, i) of a binary64
+//           matrix with global atomics; an epilogue pass evaporates, adds,
+//           refreshes the choice matrix and clears the deposit matrix.
+#include "aco_device.hpp"
+#include "aco_state.hpp"
+
+namespace aco {
+namespace {
+
+constexpr int kRowThreads = 256;
+
+__device__ __forceinline__ float evaporation_keep(float rho) {
+    return (float)(1.0 - (double)rho);  // fl32(1 - rho)
+}
+
+__device__ __forceinline__ void apply_cell(float& tau, float& choice, int32_t d, double dsum,
+                                           float keep, int alpha, int beta) {
+    const float evaporated = tau * keep;
+    tau = (float)((double)evaporated + dsum);
+    choice = choice_of(tau, heur_of(d, beta), alpha);
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
+    extern __shared__ double s_D[];  // ld binary64 accumulators
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < c.ld; j += kRowThreads) s_D[j] = 0.0;
+    __syncthreads();
+    const uint16_t* sr = c.succ + (size_t)i * c.mp;
+    const uint16_t* pr = c.pred + (size_t)i * c.mp;
+    for (int k = tid; k < c.m; k += kRowThreads) {
+        const double d = (double)c.dep[k];
+        unsafeAtomicAdd(&s_D[sr[k]], d);
+        unsafeAtomicAdd(&s_D[pr[k]], d);
+    }
+    __syncthreads();
+    const float keep = evaporation_keep(c.rho);
+    float4* trow = reinterpret_cast<float4*>(c.tau + (size_t)i * c.ld);
+    float4* crow = reinterpret_cast<float4*>(c.choice + (size_t)i * c.ld);
+    const int4* drow = reinterpret_cast<const int4*>(c.dist + (size_t)i * c.ld);
+    for (int q = tid; q < c.ld / 4; q += kRowThreads) {
+        float4 t = trow[q];
+        const int4 d = drow[q];
+        float4 ch;
+        apply_cell(t.x, ch.x, d.x, s_D[4 * q + 0], keep, c.alpha, c.beta);
+        apply_cell(t.y, ch.y, d.y, s_D[4 * q + 1], keep, c.alpha, c.beta);
+        apply_cell(t.z, ch.z, d.z, s_D[4 * q + 2], keep, c.alpha, c.beta);
+        apply_cell(t.w, ch.w, d.w, s_D[4 * q + 3], keep, c.alpha, c.beta);
+        trow[q] = t;
+        crow[q] = ch;
+    }
+}
+
+// grid (ceil(n / 256), m): thread (s, k) deposits edge (tour_k[s], tour_k[s+1]).
+__global__ __launch_bounds__(256) void k_deposit_atomic(Colony c) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    if (s >= c.n) return;
+    const uint16_t* t = c.tours + (size_t)k * c.tp;
+    const int i = t[s], j = t[s + 1];
+    const double d = (double)c.dep[k];
+    unsafeAtomicAdd(&c.delta[(size_t)i * c.ld + j], d);
+    unsafeAtomicAdd(&c.delta[(size_t)j * c.ld + i], d);
+}
+
+// grid (ceil(ld / 4 / 256), n): evaporate + deposit + choice, clear delta.
+__global__ __launch_bounds__(256) void k_update_epilogue(Colony c) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (q >= c.ld / 4) return;
+    const size_t off = (size_t)i * c.ld + 4 * (size_t)q;
+    float4 t = *reinterpret_cast<float4*>(c.tau + off);
+    const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
+    double2* dp = reinterpret_cast<double2*>(c.delta + off);
+    const double2 d01 = dp[0], d23 = dp[1];
+    const float keep = evaporation_keep(c.rho);
+    float4 ch;
+    apply_cell(t.x, ch.x, d.x, d01.x, keep, c.alpha, c.beta);
+    apply_cell(t.y, ch.y, d.y, d01.y, keep, c.alpha, c.beta);
+    apply_cell(t.z, ch.z, d.z, d23.x, keep, c.alpha, c.beta);
+    apply_cell(t.w, ch.w, d.w, d23.y, keep, c.alpha, c.beta);
+    *reinterpret_cast<float4*>(c.tau + off) = t;
+    *reinterpret_cast<float4*>(c.choice + off) = ch;
+    dp[0] = make_double2(0.0, 0.0);
+    dp[1] = make_double2(0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: C_nn by the nearest-neighbour tour from city 0 (ties to the
+// lowest index), tau0 = fl32(m / C_nn).  One workgroup; each step is an
+// argmin over the unvisited cities of the current row.
+// ---------------------------------------------------------------------------
+constexpr int kNNThreads = 1024;
+
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off));
+    return v;
+}
+
+__global__ __launch_bounds__(kNNThreads) void k_nn_tour(Colony c) {
+    __shared__ uint8_t seen[kMaxCities];
+    __shared__ unsigned long long part[kNNThreads / 64];
+    __shared__ int s_next;
+    const int tid = threadIdx.x, n = c.n;
+    for (int j = tid; j < n; j += kNNThreads) seen[j] = (j == 0);
+    __syncthreads();
+    int cur = 0;
+    long long len = 0;
+    for (int step = 1; step < n; ++step) {
+        const int32_t* row = c.dist + (size_t)cur * c.ld;
+        unsigned long long best = ~0ull;
+        for (int j = tid; j < n; j += kNNThreads)
+            if (!seen[j])
+                best = umin64(best, ((unsigned long long)(uint32_t)row[j] << 32) | (uint32_t)j);
+        best = wave_min64(best);
+        if ((tid & 63) == 0) part[tid >> 6] = best;
+        __syncthreads();
+        if (tid < 64) {
+            unsigned long long v = (tid < kNNThreads / 64) ? part[tid] : ~0ull;
+            v = wave_min64(v);
+            if (tid == 0) {
+                // n - step >= 1 cities are unseen, so v holds one of them
+                s_next = (v == ~0ull) ? 0 : (int)(v & 0xffffffffu);
+                seen[s_next] = 1;
+            }
+        }
+        __syncthreads();
+        const int next = s_next;
+        len += row[next];
+        cur = next;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        len += c.dist[(size_t)cur * c.ld + 0];
+        *c.cnn = len;
+        *c.tau0 = (float)((double)c.m / (double)len);
+        *c.best_len = 0x7fffffffffffffffLL;
+    }
+}
+
+// grid (ceil(ld / 4 / 256), n): tau <- tau0 (padding 0), choice from tau,
+// delta <- 0 when present.
+__global__ __launch_bounds__(256) void k_fill_init(Colony c) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (q >= c.ld / 4) return;
+    const size_t off = (size_t)i * c.ld + 4 * (size_t)q;
+    const float t0 = *c.tau0;
+    const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
+    const int j = 4 * q;
+    float4 t, ch;
+    t.x = (j + 0 < c.n) ? t0 : 0.0f;
+    t.y = (j + 1 < c.n) ? t0 : 0.0f;
+    t.z = (j + 2 < c.n) ? t0 : 0.0f;
+    t.w = (j + 3 < c.n) ? t0 : 0.0f;
+    ch.x = choice_of(t.x, heur_of(d.x, c.beta), c.alpha);
+    ch.y = choice_of(t.y, heur_of(d.y, c.beta), c.alpha);
+    ch.z = choice_of(t.z, heur_of(d.z, c.beta), c.alpha);
+    ch.w = choice_of(t.w, heur_of(d.w, c.beta), c.alpha);
+    *reinterpret_cast<float4*>(c.tau + off) = t;
+    *reinterpret_cast<float4*>(c.choice + off) = ch;
+    if (c.delta) {
+        double2* dp = reinterpret_cast<double2*>(c.delta + off);
+        dp[0] = make_double2(0.0, 0.0);
+        dp[1] = make_double2(0.0, 0.0);
+    }
+}
+
+// grid (ceil(ld / 4 / 256), n): choice from the current tau (checkpoint restore).
+__global__ __launch_bounds__(256) void k_refresh_choice(Colony c) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.y;
+    if (q >= c.ld / 4) return;
+    const size_t off = (size_t)i * c.ld + 4 * (size_t)q;
+    const float4 t = *reinterpret_cast<const float4*>(c.tau + off);
+    const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
+    float4 ch;
+    ch.x = choice_of(t.x, heur_of(d.x, c.beta), c.alpha);
+    ch.y = choice_of(t.y, heur_of(d.y, c.beta), c.alpha);
+    ch.z = choice_of(t.z, heur_of(d.z, c.beta), c.alpha);
+    ch.w = choice_of(t.w, heur_of(d.w, c.beta), c.alpha);
+    *reinterpret_cast<float4*>(c.choice + off) = ch;
+}
+
+// ---------------------------------------------------------------------------
+// Best-so-far: the shortest tour of this iteration (lowest ant index among
+// equals) replaces the stored one only if strictly shorter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_best(Colony c) {
+    __shared__ unsigned long long part[16];
+    __shared__ unsigned long long s_win;
+    const int tid = threadIdx.x;
+    unsigned long long best = ~0ull;
+    for (int k = tid; k < c.m; k += 1024)
+        best = umin64(best, ((unsigned long long)c.lens[k] << 16) | (unsigned)k);
+    best = wave_min64(best);
+    if ((tid & 63) == 0) part[tid >> 6] = best;
+    __syncthreads();
+    if (tid < 64) {
+        unsigned long long v = (tid < 16) ? part[tid] : ~0ull;
+        v = wave_min64(v);
+        if (tid == 0) s_win = v;
+    }
+    __syncthreads();
+    const long long len = (long long)(s_win >> 16);
+    const int k = (int)(s_win & 0xffffu);
+    const long long prev = *c.best_len;
+    if (len >= prev) return;
+    const uint16_t* src = c.tours + (size_t)k * c.tp;
+    for (int s = tid; s <= c.n; s += 1024) c.best_tour[s] = src[s];
+    __syncthreads();
+    if (tid == 0) *c.best_len = len;
+}
+
+dim3 cell_grid(const Colony& c) { return dim3((c.ld / 4 + 255) / 256, c.n); }
+
+}  // namespace
+
+hipError_t launch_update_gather(const Colony& c, hipStream_t s) {
+    hipLaunchKernelGGL(k_update_gather, dim3(c.n), dim3(kRowThreads),
+                       (size_t)c.ld * sizeof(double), s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_atomic(const Colony& c, hipStream_t s) {
+    if (!c.delta) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_deposit_atomic, dim3((c.n + 255) / 256, c.m), dim3(256), 0, s, c);
+    hipLaunchKernelGGL(k_update_epilogue, cell_grid(c), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Colony& c, hipStream_t s) {
+    hipLaunchKernelGGL(k_nn_tour, dim3(1), dim3(kNNThreads), 0, s, c);
+    hipLaunchKernelGGL(k_fill_init, cell_grid(c), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_choice(const Colony& c, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh_choice, cell_grid(c), dim3(256), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_best(const Colony& c, hipStream_t s) {
+    hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, s, c);
+    return hipGetLastError();
+}
+
+}  // namespace aco

@@ -1,0 +1,78 @@
+"""Shared pieces of the GPU parity tests: run the HIP library and the oracle
+on the same seeded instance and compare what both produce."""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+
+import oracle
+import tsp_inputs
+
+# host threads the oracle may use to construct ants in parallel (each ant is
+# still one serial oracle call, so results do not depend on it)
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tour_length(d: np.ndarray, tour: np.ndarray) -> int:
+    t = np.asarray(tour, np.int64)
+    return int(d[t[:-1], t[1:]].astype(np.int64).sum())
+
+
+def bits(a) -> np.ndarray:
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def assert_same_f32(got, want, what: str):
+    g, w = bits(got), bits(want)
+    bad = np.argwhere(g != w)
+    assert bad.size == 0, (f"{what}: {len(bad)} cells differ, first {bad[:3].tolist()} "
+                           f"got {np.asarray(got)[tuple(bad[0])]!r} want "
+                           f"{np.asarray(want)[tuple(bad[0])]!r}")
+
+
+def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic"),
+                check_choice=True):
+    """Full parity: every iteration's tours, lengths, tau (and choice) bit-exact."""
+    from paper_1101_2678_amd.aco import Colony
+
+    n = dist.shape[0]
+    log(f"  parity n={n} m={m} alpha={alpha} beta={beta} rho={rho} seed={seed} iters={iters}")
+    ref = oracle.init(dist, m, alpha, beta, rho, seed)
+    cols = {k: Colony(dist, m, alpha, beta, rho, seed, atomic=(k == "atomic")) for k in kinds}
+    for k, col in cols.items():
+        assert_same_f32(col.tau(), ref.tau, f"{k} tau0")
+        if check_choice:
+            assert_same_f32(col.choice(), ref.choice, f"{k} initial choice")
+    for it in range(iters):
+        tours, lens = oracle.construct(ref.choice, dist, m, seed, it, ORACLE_THREADS)
+        import ctypes
+
+        best = ctypes.c_int64(ref.best_len)
+        who = oracle.lib().oracle_best_of(m, lens, ctypes.byref(best))
+        if who >= 0:
+            ref.best_len, ref.best_tour = int(best.value), tours[who].copy()
+        ref.tau, ref.choice = oracle.update(ref.tau, tours, lens, dist, rho, alpha, beta)
+        ref.it += 1
+        for k, col in cols.items():
+            col.construct(it)
+            gt, gl = col.tours()
+            bad = np.nonzero((gt != tours).any(axis=1))[0]
+            assert bad.size == 0, f"{k} it={it}: tours of ants {bad[:5].tolist()} differ"
+            assert (gl == lens).all(), f"{k} it={it}: lengths differ"
+            col.update(k)
+            assert_same_f32(col.tau(), ref.tau, f"{k} it={it} tau")
+            if check_choice:
+                assert_same_f32(col.choice(), ref.choice, f"{k} it={it} choice")
+    for k, col in cols.items():
+        bt, bl = col.best()
+        assert bl == ref.best_len, f"{k}: best length {bl} != {ref.best_len}"
+        assert (bt == ref.best_tour).all(), f"{k}: best tour differs"
+        assert col.iteration == iters
+        col.close()
+    return ref

@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/aco.h, and rejects invalid arguments before touching the
+device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import tsp_inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aco.h")
+
+
+@pytest.fixture(scope="module")
+def aco():
+    from paper_1101_2678_amd import aco as mod
+
+    return mod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aco_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ["aco_init", "aco_construct", "aco_update", "aco_solve", "aco_workspace_bytes",
+                 "aco_read_tours", "aco_read_tau", "aco_destroy", "aco_status_str"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(aco):
+    missing = [f for f in declared_functions() if not hasattr(aco.lib, f)]
+    assert not missing, missing
+
+
+def test_status_strings(aco):
+    for s in range(5):
+        assert aco.lib.aco_status_str(s)
+    assert aco.lib.aco_status_str(99) == b"unknown status"
+
+
+def test_workspace_bytes(aco):
+    P = aco.Params
+    ok = P(2400, 2400, 1, 2, 0.5, 1)
+    base = aco.lib.aco_workspace_bytes(ctypes.byref(ok), 0)
+    full = aco.lib.aco_workspace_bytes(ctypes.byref(ok), 1)
+    ld = 2432
+    assert full - base >= 8 * 2400 * ld  # the binary64 deposit matrix
+    assert base >= 12 * 2400 * ld + 2 * 2400 * 2432 + 4 * 2400 * 2432
+    assert base % 256 == 0 and full % 256 == 0
+    for bad in [P(2, 5, 1, 2, 0.5, 1), P(4097, 5, 1, 2, 0.5, 1), P(10, 0, 1, 2, 0.5, 1),
+                P(10, 65536, 1, 2, 0.5, 1), P(10, 5, 3, 2, 0.5, 1), P(10, 5, 1, 5, 0.5, 1),
+                P(10, 5, 1, -1, 0.5, 1), P(10, 5, 1, 2, 0.0, 1), P(10, 5, 1, 2, 1.5, 1),
+                P(10, 5, 1, 2, float("nan"), 1)]:
+        assert aco.lib.aco_workspace_bytes(ctypes.byref(bad), 1) == 0
+
+
+def _init(aco, params, dist, ws=0x100000, nbytes=1 << 40):
+    ctx = ctypes.c_void_p()
+    d = np.ascontiguousarray(dist, np.int32)
+    st = aco.lib.aco_init(ctypes.byref(ctx), ctypes.byref(params),
+                          d.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(ws), nbytes, None)
+    return st, ctx
+
+
+def test_init_rejects_invalid_input_before_device(aco):
+    """Every rejection below happens on the host, before any HIP call."""
+    _, d = tsp_inputs.instance(10, "uniform", side=1000, seed=1)
+    P = aco.Params
+    st, ctx = _init(aco, P(10, 5, 1, 2, 0.0, 1), d)
+    assert st == aco.ACO_ERR_INVALID and not ctx.value
+    asym = d.copy()
+    asym[0, 1] += 1
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), asym)[0] == aco.ACO_ERR_INVALID
+    assert b"symmetric" in aco.lib.aco_last_error()
+    diag = d.copy()
+    diag[3, 3] = 1
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), diag)[0] == aco.ACO_ERR_INVALID
+    zero = d.copy()
+    zero[2, 5] = zero[5, 2] = 0
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), zero)[0] == aco.ACO_ERR_INVALID
+    # distances spanning too many binades for exact binary64 deposit sums
+    # (a ring of unit edges with chords of 2^30: tours from 10 to 10 * 2^30)
+    wild = np.full((10, 10), 2**30, np.int32)
+    for i in range(10):
+        wild[i, (i + 1) % 10] = wild[(i + 1) % 10, i] = 1
+    np.fill_diagonal(wild, 0)
+    assert _init(aco, P(10, 65535, 1, 2, 0.5, 1), wild)[0] == aco.ACO_ERR_INVALID
+    # workspace: misaligned, too small, NULL
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), d, ws=0x100010)[0] == aco.ACO_ERR_NOMEM
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), d, nbytes=1000)[0] == aco.ACO_ERR_NOMEM
+    assert _init(aco, P(10, 5, 1, 2, 0.5, 1), d, ws=0)[0] == aco.ACO_ERR_NOMEM
+    # NULL arguments
+    assert aco.lib.aco_init(None, None, None, None, 0, None) == aco.ACO_ERR_INVALID
+
+
+def test_calls_on_null_context(aco):
+    assert aco.lib.aco_construct(None, 0) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_update(None, 0) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_solve(None, 1, 0, None, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_sync(None) == aco.ACO_ERR_INVALID
+    aco.lib.aco_destroy(None)
+
+
+def test_probe_and_select_validation(aco):
+    assert aco.lib.aco_test_select(0, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_test_select(4097, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_test_select(10, -1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_test_select(10, 1, None, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_test_select(10, 0, None, None, None, None, None) == aco.ACO_OK
+    assert aco.lib.aco_probe_copy(16, 16, 15, None) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_probe_read(16, 32, -1, 16, None) == aco.ACO_ERR_INVALID

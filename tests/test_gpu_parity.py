@@ -1,0 +1,182 @@
+"""GPU parity: the HIP library against the oracle, element by element.
+
+Tours and integer lengths must be identical; tau and choice must be identical
+bit for bit for both update variants (the binary64 deposit sums are exact, so
+the summation order of the atomics cannot show).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import tsp_inputs
+from gpu_helpers import ORACLE_THREADS, assert_same_f32, compare_run, log, tour_length
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+# ------------------------------------------------------------------ R64 roulette
+def _adversarial_rows(n, count, rng):
+    """Rows with magnitudes from 2^-100 to 1, runs of zeros, sparse and dense
+    feasibility, one feasible city, all-zero weights, subnormal weights."""
+    rows = (rng.random((count, n)) * np.exp2(rng.integers(-100, 1, size=(count, n)))).astype(
+        np.float32)
+    kind = rng.integers(0, 8, size=count)
+    feas = (rng.random((count, n)) < rng.random((count, 1))).astype(np.uint8)
+    for q in range(count):
+        if kind[q] == 0:  # runs of zeros
+            a = rng.integers(0, n)
+            rows[q, a:a + rng.integers(1, 200)] = 0
+        elif kind[q] == 1:  # one feasible city
+            feas[q] = 0
+            feas[q, rng.integers(0, n)] = 1
+        elif kind[q] == 2:  # all weights zero
+            rows[q] = 0
+        elif kind[q] == 3:  # subnormal weights
+            rows[q] = (rng.random(n) * 2.0**-130).astype(np.float32)
+        elif kind[q] == 4:  # uniform magnitudes (typical choice rows)
+            rows[q] = rng.random(n).astype(np.float32)
+        elif kind[q] == 5:  # all feasible
+            feas[q] = 1
+        elif kind[q] == 6:  # feasible only in the last partial block
+            feas[q] = 0
+            feas[q, (n - 1) // 64 * 64:] = 1
+    feas[feas.sum(axis=1) == 0, n - 1] = 1
+    u = (rng.integers(0, 2**24, size=count) / 2**24).astype(np.float32)
+    u[::7] = 0.0
+    u[3::7] = 1.0 - 2.0**-24
+    return rows, feas, u
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 100, 511, 512, 513, 1000, 2400, 4095, 4096])
+def test_select_adversarial(n):
+    import torch
+    from paper_1101_2678_amd import aco
+
+    rng = np.random.default_rng(1000 + n)
+    count = 4000 if n <= 1000 else 1000
+    rows, feas, u = _adversarial_rows(n, count, rng)
+    log(f"  select n={n} count={count}")
+    got = aco.test_select(torch.from_numpy(rows).cuda(), torch.from_numpy(feas).cuda(),
+                          torch.from_numpy(u).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    want = oracle.r64_select_batch(rows, feas, u)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} rows differ, first {bad[:5].tolist()}"
+
+
+def test_select_non_monotone_prefix():
+    """Rows where an FP32 tree prefix inside a block exceeds later prefixes:
+    the GPU must return the same first feasible crossing as the definition."""
+    import torch
+    from paper_1101_2678_amd import aco
+
+    rng = np.random.default_rng(77)
+    rows, us = [], []
+    while len(rows) < 300:
+        w = rng.random(64).astype(np.float32)
+        w[63] = 0
+        s = oracle.s64(w)
+        if (s[:63] > s[63]).any():
+            rows.append(np.concatenate([rng.random(64).astype(np.float32), w]))
+            us.append(np.float32(1.0 - 2.0**-24))
+    rows = np.array(rows)
+    feas = np.ones_like(rows, dtype=np.uint8)
+    u = np.array(us, np.float32)
+    got = aco.test_select(torch.from_numpy(rows).cuda(), torch.from_numpy(feas).cuda(),
+                          torch.from_numpy(u).cuda()).cpu().numpy()
+    assert (got == oracle.r64_select_batch(rows, feas, u)).all()
+
+
+# ------------------------------------------------------------------ full solves
+def test_parity_config_n100():
+    """n = m = 100, uniform in [0, 10^4]^2, alpha 1, beta 2, rho 0.5, seed 1,
+    10 iterations: every tour, length, tau and choice bit-exact."""
+    _, d = tsp_inputs.instance(100, "uniform", side=10_000, seed=1)
+    compare_run(d, 100, 1, 2, 0.5, 1, 10)
+
+
+@pytest.mark.parametrize("n,m,alpha,beta,rho", [
+    (3, 4, 1, 2, 0.5), (5, 1, 1, 2, 1.0), (17, 33, 2, 4, 0.3), (63, 63, 1, 2, 0.5),
+    (64, 10, 0, 0, 0.5), (65, 65, 1, 0, 0.9), (127, 50, 0, 1, 0.5), (129, 129, 2, 1, 0.2),
+    (511, 40, 1, 2, 0.5), (512, 31, 1, 3, 0.5), (513, 64, 1, 2, 0.5), (600, 100, 1, 2, 0.1),
+])
+def test_parity_ragged(n, m, alpha, beta, rho):
+    _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=n)
+    compare_run(d, m, alpha, beta, rho, seed=n + 7, iters=3)
+
+
+@pytest.mark.parametrize("layout", ["uniform", "cluster"])
+def test_parity_n1000(layout):
+    """n = m = 1000, both layouts, first iterations bit-exact."""
+    _, d = tsp_inputs.instance(1000, layout, side=1_000_000, seed=1)
+    compare_run(d, 1000, 1, 2, 0.5, 1, 2, check_choice=False)
+
+
+def test_subnormal_choice_values():
+    """alpha 2, beta 4 on a large square drive tau^2 * eta^4 into the binary32
+    subnormal range; nothing may be flushed to zero."""
+    _, d = tsp_inputs.instance(200, "uniform", side=3_000_000, seed=5)
+    ref = compare_run(d, 50, 2, 4, 0.5, 3, 2)
+    ch = ref.choice[~np.eye(200, dtype=bool)]
+    assert (ch[ch > 0] < 2.0**-126).any(), "test does not reach subnormal values"
+
+
+# ------------------------------------------------------------------ full size, bench launch
+def test_parity_n2400_sampled():
+    """The bench workload (n = m = 2400, uniform in [0, 10^6]^2): iteration 0
+    tours of sampled ants bit-exact against the oracle; over 3 iterations every
+    tour is a permutation with its exact length, tau stays symmetric, gather
+    and atomic stay bit-identical, and the deposit total is exact."""
+    from paper_1101_2678_amd.aco import Colony
+
+    n = m = 2400
+    _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=1)
+    ref = oracle.init(d, m, 1, 2, 0.5, 1)
+    g = Colony(d, m, 1, 2, 0.5, 1, atomic=True)
+    a = Colony(d, m, 1, 2, 0.5, 1, atomic=True)
+    assert_same_f32(g.tau(), ref.tau, "tau0")
+    assert_same_f32(g.choice(), ref.choice, "choice0")
+    sample = [0, 1, 2, 1199, 2398, 2399] + list(range(17, 2400, 211))
+    for it in range(3):
+        log(f"  n=2400 iteration {it}")
+        tau_before = g.tau()
+        g.construct(it)
+        a.construct(it)
+        gt, gl = g.tours()
+        at, al = a.tours()
+        assert (gt == at).all() and (gl == al).all()
+        assert (np.sort(gt[:, :-1], axis=1) == np.arange(n)).all(), "not a permutation"
+        assert (gt[:, 0] == gt[:, -1]).all()
+        assert all(tour_length(d, gt[k]) == gl[k] for k in range(m))
+        if it == 0:
+            from concurrent.futures import ThreadPoolExecutor
+
+            with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+                res = list(ex.map(lambda k: oracle.construct_ant(ref.choice, d, 1, 0, k), sample))
+            for k, (t, ln) in zip(sample, res):
+                assert (gt[k] == t).all(), f"ant {k} differs from the oracle"
+                assert gl[k] == ln
+        g.update("gather")
+        a.update("atomic")
+        tg, ta = g.tau(), a.tau()
+        assert_same_f32(tg, ta, f"it={it} gather vs atomic tau")
+        assert (tg.view(np.uint32) == tg.T.view(np.uint32)).all()
+        # cells no tour touched only evaporate: tau' = tau * 0.5 exactly (Eq. 2)
+        untouched = np.ones((n, n), bool)
+        idx = gt[:, :-1].astype(np.int64), gt[:, 1:].astype(np.int64)
+        untouched[idx[0].ravel(), idx[1].ravel()] = False
+        untouched[idx[1].ravel(), idx[0].ravel()] = False
+        assert (tg[untouched] == tau_before[untouched] * np.float32(0.5)).all()
+    g.close()
+    a.close()
