@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark of the Ant System hot path on one MI355X.
+
+A step is one AS iteration over the resident instance: tour construction by
+all m ants (Section II, Eq. 1), then the best-so-far tour and the pheromone
+update (Eqs. 2-4, gather variant) with the choice refresh.  The default
+workload is n = m = 2400 cities uniform in [0, 10^6]^2 (the largest size the
+paper measures), alpha = 1, beta = 2, rho = 0.5, Philox seed 1; the instance
+and all state are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is ant-steps per second of the whole step
+(m (n-1) roulette selections per step).  Extra fields: per-kernel times from
+HIP events on the launch stream, update GB/s for both variants, the roofline
+of the construction kernel, live bandwidth probes, and the oracle timed on a
+bounded sample on the host (`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import tsp_inputs  # noqa: E402
+
+METRIC = ("construction ant-steps/s + update GB/s (% roofline); served solves/s and p99")
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+
+WORKLOADS = {
+    "n2400": dict(n=2400, m=2400, layout="uniform", side=1_000_000, seed=1),
+    "n1000u": dict(n=1000, m=1000, layout="uniform", side=1_000_000, seed=1),
+    "n1000c": dict(n=1000, m=1000, layout="cluster", side=1_000_000, seed=1),
+    "n100": dict(n=100, m=100, layout="uniform", side=10_000, seed=1),
+}
+ALPHA, BETA, RHO = 1, 2, 0.5
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "construct_n2400_traffic.json")
+KERNEL_SOURCES = ["paper_1101_2678_amd/csrc/construct.hip", "paper_1101_2678_amd/csrc/aco_device.hpp",
+                  "paper_1101_2678_amd/csrc/aco_state.hpp"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def construct_bytes(n: int, m: int) -> int:
+    """Algorithmic bytes of one construction launch: every ant-step streams
+    the n-entry binary32 choice row of its current city."""
+    return 4 * n * m * (n - 1)
+
+
+def gather_bytes(n: int, m: int) -> int:
+    """tau read+write, distances read, choice write (16 n^2), the succ/pred
+    neighbour tables (4 m n) and the deposits (4 m)."""
+    return 16 * n * n + 4 * m * n + 4 * m
+
+
+def atomic_bytes(n: int, m: int) -> int:
+    """tours (2 m (n+1)) and deposits (4 m) read, 2 m n binary64 atomics (8 B
+    read + 8 B write each), epilogue: tau r/w, delta r/w, dist r, choice w."""
+    return 2 * m * (n + 1) + 4 * m + 2 * m * n * 16 + 32 * n * n
+
+
+def traffic_from_profile(n_launch_units: int):
+    """HBM bytes per construction launch measured by rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), if they were taken
+    on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None, "no counter record"
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return int(rec["bytes_per_launch"]), rec.get("note", "")
+
+
+def cpu_baseline(d: np.ndarray, m: int, seconds: float):
+    """The oracle as it stands, one host thread: ants of iteration 0 built one
+    after another until `seconds` pass, then one update with m tours made by
+    tiling those ants (the update's cost does not depend on which tours)."""
+    import oracle
+
+    n = d.shape[0]
+    st = oracle.init(d, m, ALPHA, BETA, RHO, 1)
+    tours, lens = [], []
+    t0 = time.perf_counter()
+    while True:
+        t, ln = oracle.construct_ant(st.choice, d, 1, 0, len(tours))
+        tours.append(t)
+        lens.append(ln)
+        if time.perf_counter() - t0 >= seconds or len(tours) >= m:
+            break
+    t_construct = time.perf_counter() - t0
+    k = len(tours)
+    reps = (m + k - 1) // k
+    all_t = np.tile(np.array(tours), (reps, 1))[:m]
+    all_l = np.tile(np.array(lens, np.int64), reps)[:m]
+    t1 = time.perf_counter()
+    oracle.update(st.tau, all_t, all_l, d, RHO, ALPHA, BETA)
+    t_update = time.perf_counter() - t1
+    per_ant = t_construct / k
+    step_s = per_ant * m + t_update
+    return {
+        "value": m * (n - 1) / step_s,
+        "unit": "ant-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{k} ants of iteration 0 at n={n} ({k * (n - 1)} ant-steps, "
+                   f"{t_construct:.1f} s) plus one full update with m={m} tours "
+                   f"({t_update:.2f} s); step time extrapolated to m={m} ants"),
+        "construct_ant_steps_per_s": (n - 1) / per_ant,
+        "update_s": t_update,
+        "step_s_extrapolated": step_s,
+    }
+
+
+def probe_bandwidth(torch, aco):
+    """Live read bandwidth at the construction footprint (one 23 MB matrix,
+    cache resident) and at 2 GiB (HBM), plus one copy of 256 MiB that
+    calibrates the hardware byte counters in profiled runs."""
+    out = {}
+    sink = torch.empty(4096, dtype=torch.float32, device="cuda")
+    for label, nbytes, reps in [("read_23MB_GBps", 2400 * 2432 * 4, 40),
+                                ("read_2GiB_GBps", 2 << 30, 3)]:
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        aco.probe_read(buf, 1, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        aco.probe_read(buf, reps, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        out[label] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del buf
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    aco.probe_copy(dst, src)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = src.numel() * 4
+    del src, dst
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="n2400")
+    ap.add_argument("--update", choices=["gather", "atomic"], default="gather")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="host time budget of the oracle sample (0 skips it)")
+    ap.add_argument("--no-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(DESIGN.md describes how the path would shard)"}))
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_1101_2678_amd import aco
+
+    wl = WORKLOADS[args.workload]
+    n, m = wl["n"], wl["m"]
+    _, d = tsp_inputs.instance(n, wl["layout"], side=wl["side"], seed=wl["seed"])
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=True)
+    stream = torch.cuda.current_stream()
+    log(f"bench: {args.workload} n={n} m={m} {col.describe()}")
+
+    it = 0
+    for _ in range(args.warmup):
+        col.construct(it)
+        col.update(args.update)
+        it += 1
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        ev[3 * s].record(stream)
+        col.construct(it)
+        ev[3 * s + 1].record(stream)
+        col.update(args.update)
+        ev[3 * s + 2].record(stream)
+        it += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_con = np.array([ev[3 * s].elapsed_time(ev[3 * s + 1]) for s in range(K)])
+    t_upd = np.array([ev[3 * s + 1].elapsed_time(ev[3 * s + 2]) for s in range(K)])
+    log(f"bench: timed {K} steps in {wall:.3f} s")
+
+    # the other update variant, timed after the timed region on the same state
+    other = "atomic" if args.update == "gather" else "gather"
+    t_other = []
+    for _ in range(max(3, min(K, 10))):
+        col.construct(it)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        col.update(other)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_other.append(e0.elapsed_time(e1))
+        it += 1
+    t_upd_v = {args.update: float(t_upd.mean()), other: float(np.mean(t_other))}
+    best_tour, best_len = col.best()
+    col.close()
+
+    probe = None if args.no_probe else probe_bandwidth(torch, aco)
+
+    ant_steps = m * (n - 1)
+    ms_step = wall * 1e3 / K
+    con_ms = float(t_con.mean())
+    achieved = construct_bytes(n, m) / (con_ms * 1e-3) / 1e9
+    traffic, traffic_note = traffic_from_profile(ant_steps)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic, "kernel": "k_construct",
+                "algorithmic_bytes_per_launch": construct_bytes(n, m),
+                "traffic_note": traffic_note}
+    if probe:
+        roofline["measured_read_peak_same_footprint_GBps"] = round(probe["read_23MB_GBps"], 1)
+        roofline["frac_of_measured_footprint_peak"] = round(
+            achieved / probe["read_23MB_GBps"], 4)
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        log(f"bench: timing the oracle for ~{args.cpu_seconds:.0f} s on one host core")
+        cpu = cpu_baseline(d, m, args.cpu_seconds)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(ant_steps / (ms_step * 1e-3), 1),
+        "unit": "ant-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Ant System, n={n} cities {wl['layout']} in "
+                               f"[0,{wl['side']}]^2 (instance seed {wl['seed']}), m={m} ants, "
+                               f"alpha={ALPHA}, beta={BETA}, rho={RHO}, Philox seed 1, "
+                               f"{args.update} update; one step = one iteration",
+                   "n": n, "m": m, "layout": wl["layout"], "update": args.update},
+        "construct_ms": round(con_ms, 4),
+        "construct_ant_steps_per_s": round(ant_steps / (con_ms * 1e-3), 1),
+        "update_ms": {k: round(v, 4) for k, v in t_upd_v.items()},
+        "update_GBps": {
+            "gather": round(gather_bytes(n, m) / (t_upd_v["gather"] * 1e-3) / 1e9, 1),
+            "atomic": round(atomic_bytes(n, m) / (t_upd_v["atomic"] * 1e-3) / 1e9, 1)},
+        "update_frac_of_hbm_peak": {
+            "gather": round(gather_bytes(n, m) / (t_upd_v["gather"] * 1e-3) / 1e9
+                            / HBM_PEAK_GBPS, 4),
+            "atomic": round(atomic_bytes(n, m) / (t_upd_v["atomic"] * 1e-3) / 1e9
+                            / HBM_PEAK_GBPS, 4)},
+        "best_len_after_run": int(best_len),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "probe": probe,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

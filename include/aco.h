@@ -108,12 +108,14 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
                     void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* Tour construction for iteration `iter` (Section II, Eq. 1): all m ants
- * build a tour from the current choice matrix; writes tours, lengths C^k,
- * deposits fl32(1/C^k) and the best-so-far tour.  Asynchronous. */
+ * build a tour from the current choice matrix; writes tours, lengths C^k and
+ * deposits fl32(1/C^k).  One kernel launch.  Asynchronous. */
 aco_status aco_construct(aco_ctx* c, uint32_t iter);
 
-/* Pheromone update (Eqs. 2-4) from the tours of the last aco_construct, then
- * choice refresh.  Asynchronous.  ACO_ERR_STATE if no construction preceded
+/* Best-so-far tour (the shortest of the last construction, lowest ant index
+ * among equals, replaces the stored one only if strictly shorter), then the
+ * pheromone update (Eqs. 2-4) from those tours and the choice refresh.
+ * Asynchronous.  ACO_ERR_STATE if no construction preceded
  * it since the last update; ACO_ERR_INVALID for ACO_UPDATE_ATOMIC without the
  * atomic workspace. */
 aco_status aco_update(aco_ctx* c, aco_update_kind kind);

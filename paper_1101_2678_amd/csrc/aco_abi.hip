@@ -217,8 +217,7 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
 
 aco_status aco_construct(aco_ctx* c, uint32_t iter) {
     if (aco_status s = usable(c)) return s;
-    hipError_t e = aco::launch_construct(c->col, iter, c->stream);
-    if (e == hipSuccess) e = aco::launch_best(c->col, c->stream);
+    const hipError_t e = aco::launch_construct(c->col, iter, c->stream);
     if (e != hipSuccess) return device_fail(c, e, "aco_construct");
     c->pending = true;
     c->pending_iter = iter;
@@ -228,16 +227,14 @@ aco_status aco_construct(aco_ctx* c, uint32_t iter) {
 aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
     if (aco_status s = usable(c)) return s;
     if (!c->pending) return fail(ACO_ERR_STATE, "aco_update needs a preceding aco_construct");
-    hipError_t e;
-    if (kind == ACO_UPDATE_GATHER) {
-        e = aco::launch_update_gather(c->col, c->stream);
-    } else if (kind == ACO_UPDATE_ATOMIC) {
-        if (!c->has_atomic)
-            return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
-        e = aco::launch_update_atomic(c->col, c->stream);
-    } else {
+    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
         return fail(ACO_ERR_INVALID, "unknown update kind");
-    }
+    if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
+        return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
+    hipError_t e = aco::launch_best(c->col, c->stream);
+    if (e == hipSuccess)
+        e = (kind == ACO_UPDATE_GATHER) ? aco::launch_update_gather(c->col, c->stream)
+                                        : aco::launch_update_atomic(c->col, c->stream);
     if (e != hipSuccess) return device_fail(c, e, "aco_update");
     c->pending = false;
     c->next_iter = c->pending_iter + 1;

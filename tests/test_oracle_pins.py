@@ -521,3 +521,18 @@ def test_solve_deterministic_and_resumable(oracle_lib):
         oracle_lib.iterate(c, d)
     assert (a.tau.view(np.uint32) == c.tau.view(np.uint32)).all()
     assert a.best_len == c.best_len
+
+
+def test_best_of_strict_and_earliest(oracle_lib):
+    """Best-so-far: the shortest length wins, the lowest ant index among equal
+    lengths, and it replaces the stored best only if strictly shorter."""
+    import ctypes
+
+    lens = np.array([50, 40, 40, 45, 40], np.int64)
+    best = ctypes.c_int64(2**62)
+    assert oracle_lib.lib().oracle_best_of(5, lens, ctypes.byref(best)) == 1
+    assert best.value == 40
+    best = ctypes.c_int64(40)
+    assert oracle_lib.lib().oracle_best_of(5, lens, ctypes.byref(best)) == -1
+    best = ctypes.c_int64(41)
+    assert oracle_lib.lib().oracle_best_of(5, lens, ctypes.byref(best)) == 1
