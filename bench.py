@@ -75,7 +75,7 @@ def atomic_bytes(n: int, m: int) -> int:
     return 2 * m * (n + 1) + 4 * m + 2 * m * n * 16 + 32 * n * n
 
 
-def traffic_from_profile(n_launch_units: int):
+def traffic_from_profile():
     """HBM bytes per construction launch measured by rocprofv3 counters
     (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), if they were taken
     on the current kernel source."""
@@ -129,31 +129,47 @@ def cpu_baseline(d: np.ndarray, m: int, seconds: float):
     }
 
 
-def probe_bandwidth(torch, aco):
-    """Live read bandwidth at the construction footprint (one 23 MB matrix,
-    cache resident) and at 2 GiB (HBM), plus one copy of 256 MiB that
-    calibrates the hardware byte counters in profiled runs."""
+def probe_bandwidth(torch, aco, n: int, m: int):
+    """Live read bandwidth for the construction access pattern: `m` one-wave
+    workgroups each read n-1 random whole rows of n floats (aco_probe_rows),
+    from a matrix of the construction's own size (n x ld) and from larger ones
+    (160 MB: beyond L2, inside the 256 MB Infinity Cache; 1.3 GB: HBM).  Also
+    one plain 256 MiB copy (aco_probe_copy) that calibrates the hardware byte
+    counters in profiled runs."""
     out = {}
-    sink = torch.empty(4096, dtype=torch.float32, device="cuda")
-    for label, nbytes, reps in [("read_23MB_GBps", 2400 * 2432 * 4, 40),
-                                ("read_2GiB_GBps", 2 << 30, 3)]:
-        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-        aco.probe_read(buf, 1, sink)
+    ld = (n + 63) // 64 * 64
+    sink = torch.zeros(max(m, 4096), dtype=torch.float32, device="cuda")
+    for label, rows in [("same_footprint", n), ("160MB", (160 << 20) // (4 * ld)),
+                        ("1300MB", (1300 << 20) // (4 * ld))]:
+        mat = torch.rand(rows * ld, dtype=torch.float32, device="cuda")
+        aco.probe_rows(mat, rows, ld, n, m, 8, sink)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        aco.probe_read(buf, reps, sink)
+        aco.probe_rows(mat, rows, ld, n, m, n - 1, sink)
         e1.record()
         torch.cuda.synchronize()
-        out[label] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        del buf
+        ms = e0.elapsed_time(e1)
+        out[f"random_rows_{label}_GBps"] = 4.0 * n * m * (n - 1) / (ms * 1e-3) / 1e9
+        out[f"random_rows_{label}_MB"] = rows * ld * 4 / 1e6
+        del mat
+    buf = torch.ones((2 << 30) // 4, dtype=torch.float32, device="cuda")
+    aco.probe_read(buf, 1, sink)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    aco.probe_read(buf, 3, sink)
+    e1.record()
+    torch.cuda.synchronize()
+    out["stream_read_2GiB_GBps"] = buf.numel() * 4 * 3 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf
     src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     aco.probe_copy(dst, src)
     torch.cuda.synchronize()
     out["copy_calibration_bytes"] = src.numel() * 4
     del src, dst
-    return out
+    return {k: (round(v, 1) if isinstance(v, float) else v) for k, v in out.items()}
 
 
 def main():
@@ -226,22 +242,22 @@ def main():
     best_tour, best_len = col.best()
     col.close()
 
-    probe = None if args.no_probe else probe_bandwidth(torch, aco)
+    probe = None if args.no_probe else probe_bandwidth(torch, aco, n, m)
 
     ant_steps = m * (n - 1)
     ms_step = wall * 1e3 / K
     con_ms = float(t_con.mean())
     achieved = construct_bytes(n, m) / (con_ms * 1e-3) / 1e9
-    traffic, traffic_note = traffic_from_profile(ant_steps)
+    traffic, traffic_note = traffic_from_profile()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": traffic, "kernel": "k_construct",
                 "algorithmic_bytes_per_launch": construct_bytes(n, m),
                 "traffic_note": traffic_note}
     if probe:
-        roofline["measured_read_peak_same_footprint_GBps"] = round(probe["read_23MB_GBps"], 1)
-        roofline["frac_of_measured_footprint_peak"] = round(
-            achieved / probe["read_23MB_GBps"], 4)
+        ceiling = probe["random_rows_same_footprint_GBps"]
+        roofline["measured_random_row_ceiling_GBps"] = ceiling
+        roofline["frac_of_measured_random_row_ceiling"] = round(achieved / ceiling, 4)
 
     cpu = None
     if args.cpu_seconds > 0:

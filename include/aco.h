@@ -184,6 +184,15 @@ aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void
 aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
                           void* hip_stream);
 
+/* Random-row read probe: the access pattern of tour construction without its
+ * arithmetic.  `waves` one-wavefront workgroups each read `steps` whole rows
+ * of `row_len` floats from a rows x ld float matrix (device), the row of each
+ * step a hash of (workgroup, step).  Algorithmic bytes: 4 * row_len * waves *
+ * steps.  sink_dev: >= waves floats (device).  ld % 4 == 0, row_len <= 4096.
+ * Asynchronous. */
+aco_status aco_probe_rows(const float* mat_dev, int32_t rows, int32_t ld, int32_t row_len,
+                          int32_t waves, int32_t steps, float* sink_dev, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,7 @@ def _load():
         "aco_test_select": (i32, [i32, i32, vp, vp, vp, vp, vp]),
         "aco_probe_copy": (i32, [vp, vp, sz, vp]),
         "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
+        "aco_probe_rows": (i32, [vp, i32, i32, i32, i32, i32, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -217,6 +218,13 @@ def probe_copy(dst, src, stream=None):
     _check(lib.aco_probe_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
                               src.numel() * src.element_size(), _stream_handle(stream)),
            "aco_probe_copy")
+
+
+def probe_rows(mat, rows: int, ld: int, row_len: int, waves: int, steps: int, sink,
+               stream=None):
+    _check(lib.aco_probe_rows(ctypes.c_void_p(mat.data_ptr()), rows, ld, row_len, waves, steps,
+                              ctypes.c_void_p(sink.data_ptr()), _stream_handle(stream)),
+           "aco_probe_rows")
 
 
 def probe_read(src, reps: int, sink, stream=None):

@@ -347,11 +347,16 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
     if (!c) return fail(ACO_ERR_INVALID, "context is NULL");
     if (!buf || len == 0) return fail(ACO_ERR_INVALID, "buffer is NULL");
     const aco::Colony& col = c->col;
+    int dev = 0, cus = 0, lds_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
     std::snprintf(buf, len,
                   "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
-                  "update_gather_threads=256 atomic=%d",
+                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 atomic=%d",
                   aco::kCitiesPerLane, (col.n + aco::kPassCities - 1) / aco::kPassCities,
-                  (col.n + 63) / 64, col.ld, c->has_atomic ? 1 : 0);
+                  (col.n + 63) / 64, col.ld, aco::construct_occupancy(col), cus, lds_cu,
+                  c->has_atomic ? 1 : 0);
     return ACO_OK;
 }
 
@@ -390,6 +395,19 @@ aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float
     const hipError_t e = aco::launch_probe_read(src_dev, bytes, reps, sink_dev,
                                                 static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_read");
+    return ACO_OK;
+}
+
+aco_status aco_probe_rows(const float* mat_dev, int32_t rows, int32_t ld, int32_t row_len,
+                          int32_t waves, int32_t steps, float* sink_dev, void* hip_stream) {
+    if (rows < 1 || row_len < 1 || row_len > aco::kMaxCities || ld < row_len || (ld % 4) != 0)
+        return fail(ACO_ERR_INVALID, "need rows >= 1, 1 <= row_len <= 4096, ld >= row_len, ld % 4 == 0");
+    if (waves < 0 || steps < 0) return fail(ACO_ERR_INVALID, "waves and steps must be >= 0");
+    if (waves > 0 && (!mat_dev || !sink_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)mat_dev % 16) != 0) return fail(ACO_ERR_INVALID, "matrix must be 16-byte aligned");
+    const hipError_t e = aco::launch_probe_rows(mat_dev, rows, ld, row_len, waves, steps, sink_dev,
+                                                static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_rows");
     return ACO_OK;
 }
 

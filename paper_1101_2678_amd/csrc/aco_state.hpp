@@ -39,6 +39,8 @@ constexpr int kPassCities = 64 * kCitiesPerLane;
 constexpr int kMaxCities = 4096;
 
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
+// Construction workgroups (ants) resident per compute unit, or -1.
+int construct_occupancy(const Colony& c);
 hipError_t launch_best(const Colony& c, hipStream_t s);
 hipError_t launch_update_gather(const Colony& c, hipStream_t s);
 hipError_t launch_update_atomic(const Colony& c, hipStream_t s);
@@ -47,6 +49,8 @@ hipError_t launch_refresh_choice(const Colony& c, hipStream_t s);
 hipError_t launch_test_select(int n, int count, const float* rows, const uint8_t* feasible,
                               const float* u, int32_t* out, hipStream_t s);
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
+                             int steps, float* sink, hipStream_t s);
 hipError_t launch_probe_read(const void* src, size_t bytes, int reps, float* sink,
                              hipStream_t s);
 

@@ -52,7 +52,9 @@ __device__ __forceinline__ uint64_t initial_block_bits(int n, int b) {
 // Clears city j in both tabu representations (called with j uniform).
 __device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& lane_bits,
                                              uint64_t* s_vis) {
-    if (lane == 0) s_vis[j >> 6] |= 1ull << (j & 63);
+    if (lane == 0)
+        __hip_atomic_fetch_or(&s_vis[j >> 6], 1ull << (j & 63), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
     const int owner = (j & (kPassCities - 1)) >> 3;
     const int bit = ((j / kPassCities) << 3) + (j & 7);
     if (lane == owner) lane_bits &= ~(1ull << bit);
@@ -78,40 +80,66 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t bits) {
     return m;
 }
 
+// Stages the masked weights of block `b` into s_w (city 64b + t at
+// s_w[64 (b mod 8) + t]).  The block lives in pass b/8, lanes 8 (b mod 8) ..
+// 8 (b mod 8) + 7; the pass index is wave-uniform but not a compile-time
+// constant, so each pass has its own branch, and the stores are opaque to the
+// optimiser so that it cannot merge the branches into per-register selects.
 template <int P>
-__device__ __forceinline__ float masked_octet_sum(const u32x4& a, const u32x4& b, uint32_t bits) {
-    const float w0 = __uint_as_float(a.x & bit_mask<0>(bits));
-    const float w1 = __uint_as_float(a.y & bit_mask<1>(bits));
-    const float w2 = __uint_as_float(a.z & bit_mask<2>(bits));
-    const float w3 = __uint_as_float(a.w & bit_mask<3>(bits));
-    const float w4 = __uint_as_float(b.x & bit_mask<4>(bits));
-    const float w5 = __uint_as_float(b.y & bit_mask<5>(bits));
-    const float w6 = __uint_as_float(b.z & bit_mask<6>(bits));
-    const float w7 = __uint_as_float(b.w & bit_mask<7>(bits));
-    return ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7));
+__device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&wb)[P], int b,
+                                            float* s_w, int lane) {
+    const int pb = b >> 3;
+    if ((lane >> 3) != (b & 7)) return;
+    const uint32_t addr = (uint32_t)(uintptr_t)(s_w + lane * kCitiesPerLane);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (p == pb) {
+            asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:16"
+                         :
+                         : "v"(addr), "v"(wa[p]), "v"(wb[p])
+                         : "memory");
+        }
+    }
 }
 
 // One R64 roulette draw over `row` (ld-padded, zero beyond n).
 // Returns the chosen city, or -1 if no city is feasible.  Wave-uniform.
+// The masked weights stay in registers; the pass holding a candidate block
+// is staged into LDS (city j at s_w[j]) only when that block is scanned.  The
+// workgroup is one wavefront: its LDS operations execute in program order,
+// and every LDS access below uses a lane-dependent index, so the compiler
+// keeps the order.
 template <int P>
 __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, uint64_t lane_bits,
-                                        const uint64_t* s_vis, float* s_T, float u, int lane) {
+                                        const uint64_t* s_vis, float* s_T, float* s_w, float u,
+                                        int lane) {
     const int nb = (n + 63) >> 6;
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
-    u32x4 v[P][2];
+    u32x4 wa[P], wb[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int off = (p * kPassCities + lane * kCitiesPerLane) * 4;
-        v[p][0] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        v[p][1] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        float t = masked_octet_sum<P>(v[p][0], v[p][1], (uint32_t)(lane_bits >> (p * 8)));
+        const uint32_t bits = (uint32_t)(lane_bits >> (p * 8));
+        wa[p].x &= bit_mask<0>(bits);
+        wa[p].y &= bit_mask<1>(bits);
+        wa[p].z &= bit_mask<2>(bits);
+        wa[p].w &= bit_mask<3>(bits);
+        wb[p].x &= bit_mask<4>(bits);
+        wb[p].y &= bit_mask<5>(bits);
+        wb[p].z &= bit_mask<6>(bits);
+        wb[p].w &= bit_mask<7>(bits);
+        float t = ((__uint_as_float(wa[p].x) + __uint_as_float(wa[p].y)) +
+                   (__uint_as_float(wa[p].z) + __uint_as_float(wa[p].w))) +
+                  ((__uint_as_float(wb[p].x) + __uint_as_float(wb[p].y)) +
+                   (__uint_as_float(wb[p].z) + __uint_as_float(wb[p].w)));
         t = octet_pairwise(t);
         if ((lane & 7) == 7) s_T[p * 8 + (lane >> 3)] = t;
     }
-    __syncthreads();
     const float T = s_T[lane];
     const float I = s64_scan(T);
     const float total = read_lane(I, nb - 1);
@@ -122,11 +150,11 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, ui
     while (cand) {
         const int b = __builtin_ctzll(cand);
         cand &= cand - 1;
+        stage_block<P>(wa, wb, b, s_w, lane);
         const uint64_t vis = s_vis[b];
+        const float w = s_w[(b & 7) * 64 + lane];
         const bool feasible = ((vis >> lane) & 1ull) == 0ull;
-        const float c = __uint_as_float(
-            __builtin_amdgcn_raw_buffer_load_b32(rs, (b * 64 + lane) * 4, 0, 0));
-        const float s = s64_scan(feasible ? c : 0.0f);
+        const float s = s64_scan(w);
         const float eb = read_lane(E, b);
         const uint64_t hit = ballot(feasible && (eb + s) > target);
         if (hit) return b * 64 + __builtin_ctzll(hit);
@@ -138,9 +166,18 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, ui
     return b * 64 + 63 - __builtin_clzll(~s_vis[b]);
 }
 
+// Uniform draws for steps s0 .. s0+63: lane t holds u of step s0 + t.  The
+// counter words differ per lane, so the ten Philox rounds run on the vector
+// unit once per 64 steps instead of on the scalar unit every step.
+__device__ __forceinline__ float draws64(PhiloxKey key, uint32_t iter, uint32_t ant, int s0,
+                                         int lane) {
+    return uniform24(draw(key, iter, ant, (uint32_t)(s0 + lane)));
+}
+
 template <int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
+    __shared__ __align__(16) float s_w[kPassCities];
     __shared__ uint64_t s_vis[64];
     __shared__ float s_T[64];
     const int lane = threadIdx.x;
@@ -158,11 +195,13 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     if (lane == 0) s_tour[0] = (uint16_t)cur;
     mark_visited(cur, lane, lane_bits, s_vis);
 
+    float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
-        const float u = uniform24(draw(key, iter, (uint32_t)k, (uint32_t)step));
+        const int slot = (step - 1) & 63;
+        if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
+        const float u = read_lane(u64, slot);
         const float* row = c.choice + (size_t)cur * c.ld;
-        __syncthreads();
-        int j = r64_pick<P>(row, n, lane_bits, s_vis, s_T, u, lane);
+        int j = r64_pick<P>(row, n, lane_bits, s_vis, s_T, s_w, u, lane);
         // At every step n - step >= 1 cities are unvisited, so j >= 0; the
         // clamp only keeps the LDS indices in range should that ever break.
         j = j < 0 ? 0 : j;
@@ -196,6 +235,7 @@ template <int P>
 __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, int n,
                                                      const uint8_t* feasible, const float* us,
                                                      int32_t* out) {
+    __shared__ __align__(16) float s_w[kPassCities];
     __shared__ uint64_t s_vis[64];
     __shared__ float s_T[64];
     const int lane = threadIdx.x;
@@ -217,7 +257,8 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
             if (j < n && f[j]) lane_bits |= 1ull << (p * 8 + e);
         }
     __syncthreads();
-    const int j = r64_pick<P>(rows + (size_t)q * ld, n, lane_bits, s_vis, s_T, us[q], lane);
+    const int j =
+        r64_pick<P>(rows + (size_t)q * ld, n, lane_bits, s_vis, s_T, s_w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
 
@@ -237,7 +278,31 @@ hipError_t launch_select_p(int n, int count, const float* rows, const uint8_t* f
     return hipGetLastError();
 }
 
+template <int P>
+int occupancy_p(const Colony& c) {
+    int blocks = 0;
+    const size_t lds = ((size_t)(c.n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_construct<P>, 64, lds) !=
+        hipSuccess)
+        return -1;
+    return blocks;
+}
+
 }  // namespace
+
+int construct_occupancy(const Colony& c) {
+    switch ((c.n + kPassCities - 1) / kPassCities) {
+        case 1: return occupancy_p<1>(c);
+        case 2: return occupancy_p<2>(c);
+        case 3: return occupancy_p<3>(c);
+        case 4: return occupancy_p<4>(c);
+        case 5: return occupancy_p<5>(c);
+        case 6: return occupancy_p<6>(c);
+        case 7: return occupancy_p<7>(c);
+        case 8: return occupancy_p<8>(c);
+        default: return -1;
+    }
+}
 
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s) {
     switch ((c.n + kPassCities - 1) / kPassCities) {

@@ -36,7 +36,67 @@ __global__ __launch_bounds__(256) void k_probe_read(const float4* __restrict__ s
 
 constexpr int kProbeBlocks = 4096;
 
+// Random-row read probe: the memory access pattern of tour construction
+// without its arithmetic.  One wavefront per workgroup reads `steps` whole
+// rows of `row_len` floats (row pitch `ld`), lane l taking 8 consecutive
+// floats per 512-float pass; the row of step s is a hash of (workgroup, s), so
+// consecutive rows of one wavefront, and the rows of different wavefronts,
+// are independent and uniformly spread over `rows`.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+typedef unsigned int probe_u32x4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__global__ __launch_bounds__(64) void k_probe_rows(const float* mat, int rows, int ld,
+                                                   int row_len, int steps, float* sink) {
+    const int lane = threadIdx.x;
+    uint32_t acc = 0;
+    for (int s = 0; s < steps; ++s) {
+        const uint32_t h = mix32((uint32_t)blockIdx.x * 0x9E3779B9u + (uint32_t)s);
+        const int r = (int)(((uint64_t)h * (uint32_t)rows) >> 32);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(mat + (size_t)r * ld), (short)0, ((row_len + 3) & ~3) * 4,
+            0x00020000);
+        probe_u32x4 a[P], b[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int off = (p * 512 + lane * 8) * 4;
+            a[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+            b[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            acc ^= a[p].x ^ a[p].y ^ a[p].z ^ a[p].w ^ b[p].x ^ b[p].y ^ b[p].z ^ b[p].w;
+    }
+    if (acc == 0x12345678u) sink[blockIdx.x] = 1.0f;  // keeps the loads alive
+}
+
 }  // namespace
+
+hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
+                             int steps, float* sink, hipStream_t s) {
+    if (waves <= 0 || steps <= 0) return hipSuccess;
+    const dim3 g(waves), b(64);
+    switch ((row_len + 511) / 512) {
+        case 1: hipLaunchKernelGGL(k_probe_rows<1>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 2: hipLaunchKernelGGL(k_probe_rows<2>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 3: hipLaunchKernelGGL(k_probe_rows<3>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 4: hipLaunchKernelGGL(k_probe_rows<4>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 5: hipLaunchKernelGGL(k_probe_rows<5>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 6: hipLaunchKernelGGL(k_probe_rows<6>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 7: hipLaunchKernelGGL(k_probe_rows<7>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 8: hipLaunchKernelGGL(k_probe_rows<8>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     const size_t n16 = bytes / 16;
