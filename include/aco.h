@@ -163,15 +163,75 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len);
 
 /* R64 roulette on `count` independent rows through the same device code the
  * construction kernel uses (Section II, Eq. 1).
+ *   tile          cities per lane of the construction tile to use (4 or 8;
+ *                 4 only for n <= 1024); the result must not depend on it
  *   rows_dev      count rows of `ld` floats (device), ld = n rounded up to
  *                 64; columns n..ld-1 must be zero
  *   feasible_dev  count*n uint8 (device), non-zero = city may be chosen
  *   u_dev         count floats in [0, 1) (device)
  *   out_dev       count int32 (device): the chosen city, -1 if none feasible
  * Asynchronous on hip_stream. */
-aco_status aco_test_select(int32_t n, int32_t count, const float* rows_dev,
+aco_status aco_test_select(int32_t tile, int32_t n, int32_t count, const float* rows_dev,
                            const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
                            void* hip_stream);
+
+/* ---- construction tiles ------------------------------------------------ */
+
+/* The construction kernel spreads a choice row over a wavefront with
+ * `cities_per_lane` (4 or 8) consecutive cities per lane per pass (the
+ * paper's city tiling, Section III-A).  The tile changes speed only, never
+ * results.  aco_set_tile sets the tile for instance sizes n_lo..n_hi (tile 4
+ * only for n <= 1024); contexts and batches created afterwards use it.  The
+ * table is process-wide and not thread-safe.  Default: 8 for every n. */
+aco_status aco_set_tile(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane);
+int32_t aco_get_tile(int32_t n);
+
+/* Autotuner: for each of the `count` strictly increasing instance sizes
+ * (3..4096), builds a synthetic uniform instance with m = n on d_workspace
+ * (>= aco_workspace_bytes for the largest size with m = n, without the
+ * atomic part), times `reps` constructions with every supported tile, and
+ * sets the tile table so that bucket i, sizes (sizes[i-1], sizes[i]] (the
+ * last bucket up to 4096), uses the fastest tile.  chosen (count int32),
+ * ms_tile4 and ms_tile8 (count floats, -1 where unsupported) may be NULL.
+ * Synchronous; overwrites the workspace. */
+aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes, int32_t count,
+                        int32_t reps, void* hip_stream, int32_t* chosen, float* ms_tile4,
+                        float* ms_tile8);
+
+/* ---- batches: many independent instances advanced together --------------- */
+
+typedef struct aco_batch aco_batch; /* opaque; host memory owned by the library */
+
+/* Exact device bytes for a batch of `count` instances (params: count
+ * entries, host).  Returns 0 if any parameter set is invalid. */
+size_t aco_batch_workspace_bytes(int32_t count, const aco_params* params);
+
+/* Creates a batch of `count` independent instances (1..65535): instance q has
+ * params[q] and the n_q*n_q distances dist_hosts[q] (host, borrowed).  All
+ * state lives in d_workspace (caller-owned, 256-byte aligned, >=
+ * aco_batch_workspace_bytes).  Instances are scheduled largest n first.
+ * Every instance starts at iteration 0 and computes exactly what a context of
+ * its own computes with the gather update.  Synchronous. */
+aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* params,
+                          const int32_t* const* dist_hosts, void* d_workspace, size_t ws_bytes,
+                          void* hip_stream);
+
+/* Advances every instance by `iters` iterations (construction, best-so-far,
+ * gather update): three launches per iteration for the whole batch.  With
+ * use_graph != 0 the launches are captured once into a HIP graph (kept for
+ * the next call with the same `iters`) and replayed; this needs a
+ * non-default stream.  Asynchronous. */
+aco_status aco_batch_run(aco_batch* b, uint32_t iters, int32_t use_graph);
+
+/* Per-instance reads (q in caller order).  Synchronous. */
+aco_status aco_batch_read_best(aco_batch* b, int32_t q, uint16_t* best_tour_host,
+                               int64_t* best_len_host);
+aco_status aco_batch_read_tours(aco_batch* b, int32_t q, uint16_t* tours_host,
+                                int64_t* lens_host);
+aco_status aco_batch_read_tau(aco_batch* b, int32_t q, float* tau_host);
+aco_status aco_batch_get_iter(aco_batch* b, int32_t q, uint32_t* iter);
+aco_status aco_batch_sync(aco_batch* b);
+void aco_batch_destroy(aco_batch* b);
 
 /* Streams `bytes` (multiple of 16) from src_dev to dst_dev with 16-byte loads
  * and stores: a plain copy kernel of known traffic, used to calibrate

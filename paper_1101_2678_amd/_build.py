@@ -23,13 +23,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libaco.so")
-SOURCES = ["construct.hip", "update.hip", "probe.hip", "aco_abi.hip"]
+SOURCES = ["construct.hip", "update.hip", "probe.hip", "aco_abi.hip", "batch.hip"]
 ARCH = os.environ.get("ACO_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-ffp-contract=off",
     "-fno-gpu-flush-denormals-to-zero",

@@ -56,7 +56,19 @@ def _load():
         "aco_status_str": (c.c_char_p, [i32]),
         "aco_last_error": (c.c_char_p, []),
         "aco_describe": (i32, [vp, c.c_char_p, sz]),
-        "aco_test_select": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+        "aco_test_select": (i32, [i32, i32, i32, vp, vp, vp, vp, vp]),
+        "aco_set_tile": (i32, [i32, i32, i32]),
+        "aco_get_tile": (i32, [i32]),
+        "aco_autotune": (i32, [vp, sz, vp, i32, i32, vp, vp, vp, vp]),
+        "aco_batch_workspace_bytes": (sz, [i32, vp]),
+        "aco_batch_init": (i32, [c.POINTER(vp), i32, vp, vp, vp, sz, vp]),
+        "aco_batch_run": (i32, [vp, u32, i32]),
+        "aco_batch_read_best": (i32, [vp, i32, vp, vp]),
+        "aco_batch_read_tours": (i32, [vp, i32, vp, vp]),
+        "aco_batch_read_tau": (i32, [vp, i32, vp]),
+        "aco_batch_get_iter": (i32, [vp, i32, c.POINTER(u32)]),
+        "aco_batch_sync": (i32, [vp]),
+        "aco_batch_destroy": (None, [vp]),
         "aco_probe_copy": (i32, [vp, vp, sz, vp]),
         "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
         "aco_probe_rows": (i32, [vp, i32, i32, i32, i32, i32, vp, vp]),
@@ -194,7 +206,7 @@ class Colony:
             pass
 
 
-def test_select(rows, feasible, u, stream=None):
+def test_select(rows, feasible, u, tile: int = 8, stream=None):
     """R64 roulette on independent rows through the construction kernel's code.
     rows: (count, n) float32 torch tensor on the GPU; feasible: (count, n)
     uint8; u: (count,) float32.  Returns a (count,) int32 tensor."""
@@ -207,11 +219,118 @@ def test_select(rows, feasible, u, stream=None):
     feas = feasible.to(torch.uint8).contiguous()
     uu = u.to(torch.float32).contiguous()
     out = torch.empty(count, dtype=torch.int32, device=rows.device)
-    _check(lib.aco_test_select(n, count, ctypes.c_void_p(padded.data_ptr()),
+    _check(lib.aco_test_select(tile, n, count, ctypes.c_void_p(padded.data_ptr()),
                                ctypes.c_void_p(feas.data_ptr()), ctypes.c_void_p(uu.data_ptr()),
                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
            "aco_test_select")
     return out
+
+
+def set_tile(n_lo: int, n_hi: int, cities_per_lane: int):
+    _check(lib.aco_set_tile(n_lo, n_hi, cities_per_lane), "aco_set_tile")
+
+
+def get_tile(n: int) -> int:
+    return int(lib.aco_get_tile(n))
+
+
+def autotune(sizes, reps: int = 3, device="cuda", stream=None):
+    """Times every construction tile on synthetic instances of the given
+    sizes (m = n) and sets the tile table; returns (chosen, ms4, ms8)."""
+    import torch
+
+    sizes = np.ascontiguousarray(sorted(int(x) for x in sizes), np.int32)
+    k = len(sizes)
+    nbytes = workspace_bytes(int(sizes[-1]), int(sizes[-1]), atomic=False)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    chosen = np.zeros(k, np.int32)
+    ms4 = np.zeros(k, np.float32)
+    ms8 = np.zeros(k, np.float32)
+    _check(lib.aco_autotune(ctypes.c_void_p(ws.data_ptr()), nbytes,
+                            sizes.ctypes.data_as(ctypes.c_void_p), k, reps,
+                            _stream_handle(stream), chosen.ctypes.data_as(ctypes.c_void_p),
+                            ms4.ctypes.data_as(ctypes.c_void_p),
+                            ms8.ctypes.data_as(ctypes.c_void_p)), "aco_autotune")
+    return chosen, ms4, ms8
+
+
+class Batch:
+    """Many independent instances resident on one GPU, advanced together.
+
+    dists: list of (n_q, n_q) int32 matrices; params: list of dicts with keys
+    m, alpha, beta, rho, seed (n comes from the matrix).  All launches go to
+    `stream` (default: a new non-default torch stream, needed for graphs).
+    """
+
+    def __init__(self, dists, params, device="cuda", stream=None):
+        import torch
+
+        self.count = len(dists)
+        self._dists = [np.ascontiguousarray(d, dtype=np.int32) for d in dists]
+        arr = (Params * self.count)()
+        for q, (d, p) in enumerate(zip(self._dists, params)):
+            arr[q] = Params(d.shape[0], p["m"], p.get("alpha", 1), p.get("beta", 2),
+                            p.get("rho", 0.5), p.get("seed", 1))
+        self.params = arr
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        nbytes = lib.aco_batch_workspace_bytes(self.count, arr)
+        if nbytes == 0:
+            _check(ACO_ERR_INVALID, "aco_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ptrs = (ctypes.c_void_p * self.count)(*[d.ctypes.data for d in self._dists])
+        self._b = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.aco_batch_init(ctypes.byref(self._b), self.count, arr, ptrs,
+                                      ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                      _stream_handle(self.stream)), "aco_batch_init")
+
+    def run(self, iters: int, graph: bool = True):
+        _check(lib.aco_batch_run(self._b, iters, 1 if graph else 0), "aco_batch_run")
+
+    def sync(self):
+        _check(lib.aco_batch_sync(self._b), "aco_batch_sync")
+
+    def best(self, q: int):
+        n = self._dists[q].shape[0]
+        tour = np.empty(n + 1, np.uint16)
+        length = ctypes.c_int64()
+        _check(lib.aco_batch_read_best(self._b, q, tour.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(length)), "aco_batch_read_best")
+        return tour, int(length.value)
+
+    def tours(self, q: int):
+        n = self._dists[q].shape[0]
+        m = self.params[q].m
+        t = np.empty((m, n + 1), np.uint16)
+        ln = np.empty(m, np.int64)
+        _check(lib.aco_batch_read_tours(self._b, q, t.ctypes.data_as(ctypes.c_void_p),
+                                        ln.ctypes.data_as(ctypes.c_void_p)),
+               "aco_batch_read_tours")
+        return t, ln
+
+    def tau(self, q: int):
+        n = self._dists[q].shape[0]
+        out = np.empty((n, n), np.float32)
+        _check(lib.aco_batch_read_tau(self._b, q, out.ctypes.data_as(ctypes.c_void_p)),
+               "aco_batch_read_tau")
+        return out
+
+    def iteration(self, q: int) -> int:
+        v = ctypes.c_uint32()
+        _check(lib.aco_batch_get_iter(self._b, q, ctypes.byref(v)), "aco_batch_get_iter")
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib.aco_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def probe_copy(dst, src, stream=None):

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "aco.h"
+#include "aco_host.hpp"
 #include "aco_state.hpp"
 
 struct aco_ctx {
@@ -24,7 +25,8 @@ struct aco_ctx {
     bool has_atomic;
 };
 
-namespace {
+namespace aco {
+namespace host {
 
 thread_local std::string g_error;
 
@@ -33,31 +35,22 @@ aco_status fail(aco_status s, const std::string& why) {
     return s;
 }
 
-aco_status device_fail(aco_ctx* c, hipError_t e, const char* where) {
-    if (c) c->poisoned = true;
+aco_status device_fail(bool* poisoned, hipError_t e, const char* where) {
+    if (poisoned) *poisoned = true;
     return fail(ACO_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
-
-constexpr size_t kAlign = 256;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 bool params_valid(const aco_params* p, std::string* why) {
     if (!p) return (*why = "params is NULL", false);
-    if (p->n < 3 || p->n > aco::kMaxCities) return (*why = "n must be in [3, 4096]", false);
+    if (p->n < 3 || p->n > kMaxCities) return (*why = "n must be in [3, 4096]", false);
     if (p->m < 1 || p->m > 65535) return (*why = "m must be in [1, 65535]", false);
     if (p->alpha < 0 || p->alpha > 2) return (*why = "alpha must be 0, 1 or 2", false);
     if (p->beta < 0 || p->beta > 4) return (*why = "beta must be in [0, 4]", false);
     if (!(p->rho > 0.0f && p->rho <= 1.0f)) return (*why = "rho must be in (0, 1]", false);
     return true;
 }
-
-// Byte offsets of every array inside the workspace.
-struct Layout {
-    int32_t ld, tp, mp;
-    size_t tau, choice, dist, tours, succ, pred, lens, dep, best_len, best_tour, cnn, tau0,
-        delta, base_end, atomic_end;
-};
 
 Layout make_layout(const aco_params& p) {
     Layout L{};
@@ -83,6 +76,7 @@ Layout make_layout(const aco_params& p) {
     L.best_tour = take((size_t)L.tp * sizeof(uint16_t));
     L.cnn = take(sizeof(int64_t));
     L.tau0 = take(sizeof(float));
+    L.iter = take(sizeof(uint32_t));
     L.base_end = off;
     L.delta = take(cells * sizeof(double));
     L.atomic_end = off;
@@ -118,6 +112,83 @@ bool dist_valid(const int32_t* d, int n, int m, std::string* why) {
     return true;
 }
 
+Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile) {
+    Colony col{};
+    col.n = p.n;
+    col.m = p.m;
+    col.ld = L.ld;
+    col.tp = L.tp;
+    col.mp = L.mp;
+    col.alpha = p.alpha;
+    col.beta = p.beta;
+    col.rho = p.rho;
+    col.seed = p.seed;
+    col.tau = reinterpret_cast<float*>(base + L.tau);
+    col.choice = reinterpret_cast<float*>(base + L.choice);
+    col.dist = reinterpret_cast<int32_t*>(base + L.dist);
+    col.tours = reinterpret_cast<uint16_t*>(base + L.tours);
+    col.succ = reinterpret_cast<uint16_t*>(base + L.succ);
+    col.pred = reinterpret_cast<uint16_t*>(base + L.pred);
+    col.lens = reinterpret_cast<int64_t*>(base + L.lens);
+    col.dep = reinterpret_cast<float*>(base + L.dep);
+    col.best_len = reinterpret_cast<int64_t*>(base + L.best_len);
+    col.best_tour = reinterpret_cast<uint16_t*>(base + L.best_tour);
+    col.cnn = reinterpret_cast<int64_t*>(base + L.cnn);
+    col.tau0 = reinterpret_cast<float*>(base + L.tau0);
+    col.iter_dev = reinterpret_cast<uint32_t*>(base + L.iter);
+    col.delta = with_delta ? reinterpret_cast<double*>(base + L.delta) : nullptr;
+    col.tile = tile;
+    return col;
+}
+
+hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t base_bytes,
+                           hipStream_t stream) {
+    hipError_t e = hipMemsetAsync(col.tau, 0, base_bytes, stream);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(col.dist, (size_t)col.ld * sizeof(int32_t), dist_host,
+                             (size_t)col.n * sizeof(int32_t), (size_t)col.n * sizeof(int32_t),
+                             (size_t)col.n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_init(col, stream);
+    return e;
+}
+
+// Construction tile per instance size.  Default: 8 cities per lane.
+namespace {
+int8_t g_tile[kMaxCities + 1];
+bool g_tile_init = false;
+void ensure_tiles() {
+    if (g_tile_init) return;
+    for (int n = 0; n <= kMaxCities; ++n) g_tile[n] = 8;
+    g_tile_init = true;
+}
+}  // namespace
+
+int tile_for(int n) {
+    ensure_tiles();
+    return (n >= 0 && n <= kMaxCities) ? g_tile[n] : 8;
+}
+
+bool set_tile_range(int lo, int hi, int tile) {
+    ensure_tiles();
+    if (lo < 1 || hi > kMaxCities || lo > hi) return false;
+    for (int n = lo; n <= hi; ++n)
+        if (!tile_supported(tile, n)) return false;
+    for (int n = lo; n <= hi; ++n) g_tile[n] = (int8_t)tile;
+    return true;
+}
+
+}  // namespace host
+}  // namespace aco
+
+namespace {
+
+using aco::host::fail;
+using aco::host::g_error;
+
+aco_status device_fail(aco_ctx* c, hipError_t e, const char* where) {
+    return aco::host::device_fail(c ? &c->poisoned : nullptr, e, where);
+}
+
 aco_status usable(aco_ctx* c) {
     if (!c) return fail(ACO_ERR_INVALID, "context is NULL");
     if (c->poisoned) return fail(ACO_ERR_STATE, "context poisoned by an earlier device error");
@@ -149,8 +220,8 @@ const char* aco_last_error(void) { return g_error.c_str(); }
 
 size_t aco_workspace_bytes(const aco_params* p, int32_t with_atomic) {
     std::string why;
-    if (!params_valid(p, &why)) return 0;
-    const Layout L = make_layout(*p);
+    if (!aco::host::params_valid(p, &why)) return 0;
+    const aco::host::Layout L = aco::host::make_layout(*p);
     return with_atomic ? L.atomic_end : L.base_end;
 }
 
@@ -160,51 +231,23 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     if (!out) return fail(ACO_ERR_INVALID, "out is NULL");
     *out = nullptr;
     std::string why;
-    if (!params_valid(p, &why)) return fail(ACO_ERR_INVALID, why);
+    if (!aco::host::params_valid(p, &why)) return fail(ACO_ERR_INVALID, why);
     if (!dist_host) return fail(ACO_ERR_INVALID, "dist_host is NULL");
-    if (!dist_valid(dist_host, p->n, p->m, &why)) return fail(ACO_ERR_INVALID, why);
-    const Layout L = make_layout(*p);
-    if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+    if (!aco::host::dist_valid(dist_host, p->n, p->m, &why)) return fail(ACO_ERR_INVALID, why);
+    const aco::host::Layout L = aco::host::make_layout(*p);
+    if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
         return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
     if (ws_bytes < L.base_end)
         return fail(ACO_ERR_NOMEM, "workspace smaller than aco_workspace_bytes(p, 0)");
 
     aco_ctx* c = new (std::nothrow) aco_ctx();
     if (!c) return fail(ACO_ERR_NOMEM, "host allocation failed");
-    char* base = static_cast<char*>(d_workspace);
-    aco::Colony& col = c->col;
-    col.n = p->n;
-    col.m = p->m;
-    col.ld = L.ld;
-    col.tp = L.tp;
-    col.mp = L.mp;
-    col.alpha = p->alpha;
-    col.beta = p->beta;
-    col.rho = p->rho;
-    col.seed = p->seed;
-    col.tau = reinterpret_cast<float*>(base + L.tau);
-    col.choice = reinterpret_cast<float*>(base + L.choice);
-    col.dist = reinterpret_cast<int32_t*>(base + L.dist);
-    col.tours = reinterpret_cast<uint16_t*>(base + L.tours);
-    col.succ = reinterpret_cast<uint16_t*>(base + L.succ);
-    col.pred = reinterpret_cast<uint16_t*>(base + L.pred);
-    col.lens = reinterpret_cast<int64_t*>(base + L.lens);
-    col.dep = reinterpret_cast<float*>(base + L.dep);
-    col.best_len = reinterpret_cast<int64_t*>(base + L.best_len);
-    col.best_tour = reinterpret_cast<uint16_t*>(base + L.best_tour);
-    col.cnn = reinterpret_cast<int64_t*>(base + L.cnn);
-    col.tau0 = reinterpret_cast<float*>(base + L.tau0);
     c->has_atomic = ws_bytes >= L.atomic_end;
-    col.delta = c->has_atomic ? reinterpret_cast<double*>(base + L.delta) : nullptr;
+    c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic,
+                              aco::host::tile_for(p->n));
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ws_bytes = ws_bytes;
-
-    hipError_t e = hipMemsetAsync(base, 0, L.base_end, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(col.dist, (size_t)L.ld * sizeof(int32_t), dist_host,
-                             (size_t)p->n * sizeof(int32_t), (size_t)p->n * sizeof(int32_t),
-                             (size_t)p->n, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = aco::launch_init(col, c->stream);
+    hipError_t e = aco::host::upload_and_init(c->col, dist_host, L.base_end, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         aco_status s = device_fail(c, e, "aco_init");
@@ -214,6 +257,15 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     *out = c;
     return ACO_OK;
 }
+
+aco_status aco_set_tile(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane) {
+    if (!aco::host::set_tile_range(n_lo, n_hi, cities_per_lane))
+        return fail(ACO_ERR_INVALID,
+                    "tile must be 8 (any n) or 4 (n <= 1024) over 1 <= n_lo <= n_hi <= 4096");
+    return ACO_OK;
+}
+
+int32_t aco_get_tile(int32_t n) { return aco::host::tile_for(n); }
 
 aco_status aco_construct(aco_ctx* c, uint32_t iter) {
     if (aco_status s = usable(c)) return s;
@@ -351,26 +403,28 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    const int pass = 64 * col.tile;
     std::snprintf(buf, len,
                   "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
                   "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 atomic=%d",
-                  aco::kCitiesPerLane, (col.n + aco::kPassCities - 1) / aco::kPassCities,
-                  (col.n + 63) / 64, col.ld, aco::construct_occupancy(col), cus, lds_cu,
-                  c->has_atomic ? 1 : 0);
+                  col.tile, (col.n + pass - 1) / pass, (col.n + 63) / 64, col.ld,
+                  aco::construct_occupancy(col), cus, lds_cu, c->has_atomic ? 1 : 0);
     return ACO_OK;
 }
 
-aco_status aco_test_select(int32_t n, int32_t count, const float* rows_dev,
+aco_status aco_test_select(int32_t tile, int32_t n, int32_t count, const float* rows_dev,
                            const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
                            void* hip_stream) {
     if (n < 1 || n > aco::kMaxCities) return fail(ACO_ERR_INVALID, "n must be in [1, 4096]");
+    if (!aco::tile_supported(tile, n))
+        return fail(ACO_ERR_INVALID, "tile must be 8 (any n) or 4 (n <= 1024)");
     if (count < 0) return fail(ACO_ERR_INVALID, "count must be >= 0");
     if (count > 0 && (!rows_dev || !feasible_dev || !u_dev || !out_dev))
         return fail(ACO_ERR_INVALID, "NULL device pointer");
     if (((uintptr_t)rows_dev % 16) != 0)
         return fail(ACO_ERR_INVALID, "rows must be 16-byte aligned");
-    const hipError_t e = aco::launch_test_select(n, count, rows_dev, feasible_dev, u_dev, out_dev,
-                                                 static_cast<hipStream_t>(hip_stream));
+    const hipError_t e = aco::launch_test_select(tile, n, count, rows_dev, feasible_dev, u_dev,
+                                                 out_dev, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return device_fail(nullptr, e, "aco_test_select");
     return ACO_OK;
 }

@@ -30,15 +30,25 @@ struct Colony {
     int64_t* cnn;        // nearest-neighbour tour length
     float* tau0;         // m / C_nn
     double* delta;       // n x ld binary64 deposits (atomic update), or null
+    uint32_t* iter_dev;  // next iteration (batched path; advanced on the device)
+    int32_t tile;        // construction tile: cities per lane per pass (4 or 8)
 };
 
-// Cities each lane handles per pass of the construction kernel, and the
-// number of cities one pass of a wavefront covers.
-constexpr int kCitiesPerLane = 8;
-constexpr int kPassCities = 64 * kCitiesPerLane;
 constexpr int kMaxCities = 4096;
+constexpr int kMaxTile4Cities = 1024;  // tile 4 holds 16 passes of 256 cities at most
 
+// Whether the construction kernel has a variant with `tile` cities per lane
+// for n cities.
+bool tile_supported(int tile, int n);
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
+// One workgroup per entry of antmap: (colony << 16) | ant.  max_n bounds the
+// tour kept in LDS.
+hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
+                                  int max_n, hipStream_t s);
+hipError_t launch_best_batch(const Colony* cols, int count, hipStream_t s);
+// One workgroup per entry of rowmap: (colony << 16) | row.
+hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap, int total_rows,
+                                      int max_ld, hipStream_t s);
 // Construction workgroups (ants) resident per compute unit, or -1.
 int construct_occupancy(const Colony& c);
 hipError_t launch_best(const Colony& c, hipStream_t s);
@@ -46,8 +56,9 @@ hipError_t launch_update_gather(const Colony& c, hipStream_t s);
 hipError_t launch_update_atomic(const Colony& c, hipStream_t s);
 hipError_t launch_init(const Colony& c, hipStream_t s);
 hipError_t launch_refresh_choice(const Colony& c, hipStream_t s);
-hipError_t launch_test_select(int n, int count, const float* rows, const uint8_t* feasible,
-                              const float* u, int32_t* out, hipStream_t s);
+hipError_t launch_test_select(int tile, int n, int count, const float* rows,
+                              const uint8_t* feasible, const float* u, int32_t* out,
+                              hipStream_t s);
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
                              int steps, float* sink, hipStream_t s);

@@ -1,0 +1,395 @@
+// batch.hip -- many independent Ant System instances advanced together, and
+// the construction-tile autotuner.
+//
+// A batch keeps every instance resident in one caller-owned workspace.  One
+// AS iteration of the whole batch is three launches: construction of every
+// ant of every instance (one workgroup per ant, instances ordered largest n
+// first so the longest tours start first), the best-so-far of every
+// instance, and the gather update of every row of every instance.  Each
+// instance keeps its own iteration counter on the device, so the launches of
+// `iters` iterations can be captured once into a HIP graph and replayed.
+// Every instance computes exactly what it computes alone (same kernels' code,
+// same Philox keys), whatever the batch around it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "aco.h"
+#include "aco_host.hpp"
+#include "aco_state.hpp"
+
+using aco::host::fail;
+
+struct aco_batch {
+    int32_t count = 0;
+    std::vector<aco::Colony> cols;     // caller order
+    std::vector<int> order;            // launch position -> caller index
+    aco::Colony* d_cols = nullptr;     // launch order
+    uint32_t* d_antmap = nullptr;      // (position << 16) | ant
+    uint32_t* d_rowmap = nullptr;      // (position << 16) | row
+    int total_ants = 0, total_rows = 0, max_n = 0, max_ld = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t graph_iters = 0;
+    bool poisoned = false;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> inst_off;
+    std::vector<aco::host::Layout> inst;
+    size_t cols_off = 0, antmap_off = 0, rowmap_off = 0, end = 0;
+    int total_ants = 0, total_rows = 0;
+};
+
+bool batch_layout(int32_t count, const aco_params* params, BatchLayout* B, std::string* why) {
+    if (count < 1 || count > 65535) return (*why = "count must be in [1, 65535]", false);
+    if (!params) return (*why = "params is NULL", false);
+    size_t off = 0;
+    B->inst_off.resize(count);
+    B->inst.resize(count);
+    for (int q = 0; q < count; ++q) {
+        if (!aco::host::params_valid(&params[q], why)) {
+            *why = "instance " + std::to_string(q) + ": " + *why;
+            return false;
+        }
+        B->inst[q] = aco::host::make_layout(params[q]);
+        B->inst_off[q] = off;
+        off += aco::host::round_up(B->inst[q].base_end, aco::host::kAlign);
+        B->total_ants += params[q].m;
+        B->total_rows += params[q].n;
+    }
+    B->cols_off = off;
+    off += aco::host::round_up((size_t)count * sizeof(aco::Colony), aco::host::kAlign);
+    B->antmap_off = off;
+    off += aco::host::round_up((size_t)B->total_ants * sizeof(uint32_t), aco::host::kAlign);
+    B->rowmap_off = off;
+    off += aco::host::round_up((size_t)B->total_rows * sizeof(uint32_t), aco::host::kAlign);
+    B->end = off;
+    return true;
+}
+
+aco_status batch_usable(aco_batch* b) {
+    if (!b) return fail(ACO_ERR_INVALID, "batch is NULL");
+    if (b->poisoned) return fail(ACO_ERR_STATE, "batch poisoned by an earlier device error");
+    return ACO_OK;
+}
+
+aco_status batch_device_fail(aco_batch* b, hipError_t e, const char* where) {
+    return aco::host::device_fail(b ? &b->poisoned : nullptr, e, where);
+}
+
+hipError_t enqueue_iterations(aco_batch* b, uint32_t iters) {
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < iters && e == hipSuccess; ++i) {
+        e = aco::launch_construct_batch(b->d_cols, b->d_antmap, b->total_ants, b->max_n,
+                                        b->stream);
+        if (e == hipSuccess) e = aco::launch_best_batch(b->d_cols, b->count, b->stream);
+        if (e == hipSuccess)
+            e = aco::launch_update_gather_batch(b->d_cols, b->d_rowmap, b->total_rows, b->max_ld,
+                                                b->stream);
+    }
+    return e;
+}
+
+void drop_graph(aco_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_iters = 0;
+}
+
+// ---- synthetic instance for the autotuner: distinct points uniform in
+// [0, 10^6]^2 from a 64-bit xorshift stream, nint Euclidean distances.
+struct Xorshift {
+    uint64_t s;
+    uint64_t next() {
+        s ^= s << 13;
+        s ^= s >> 7;
+        s ^= s << 17;
+        return s;
+    }
+};
+
+std::vector<int32_t> tuning_instance(int n) {
+    Xorshift g{0x9E3779B97F4A7C15ull ^ (uint64_t)n};
+    std::vector<int64_t> x, y;
+    std::unordered_set<uint64_t> seen;
+    while ((int)x.size() < n) {
+        const int64_t px = (int64_t)(g.next() % 1000001ull), py = (int64_t)(g.next() % 1000001ull);
+        if (seen.insert(((uint64_t)px << 32) | (uint64_t)py).second) {
+            x.push_back(px);
+            y.push_back(py);
+        }
+    }
+    std::vector<int32_t> d((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const double dx = (double)(x[i] - x[j]), dy = (double)(y[i] - y[j]);
+            d[(size_t)i * n + j] = (int32_t)std::floor(std::sqrt(dx * dx + dy * dy) + 0.5);
+        }
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t aco_batch_workspace_bytes(int32_t count, const aco_params* params) {
+    BatchLayout B;
+    std::string why;
+    if (!batch_layout(count, params, &B, &why)) return 0;
+    return B.end;
+}
+
+aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* params,
+                          const int32_t* const* dist_hosts, void* d_workspace, size_t ws_bytes,
+                          void* hip_stream) {
+    aco::host::g_error.clear();
+    if (!out) return fail(ACO_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchLayout B;
+    std::string why;
+    if (!batch_layout(count, params, &B, &why)) return fail(ACO_ERR_INVALID, why);
+    if (!dist_hosts) return fail(ACO_ERR_INVALID, "dist_hosts is NULL");
+    for (int q = 0; q < count; ++q) {
+        if (!dist_hosts[q]) return fail(ACO_ERR_INVALID, "dist_hosts[" + std::to_string(q) + "] is NULL");
+        if (!aco::host::dist_valid(dist_hosts[q], params[q].n, params[q].m, &why))
+            return fail(ACO_ERR_INVALID, "instance " + std::to_string(q) + ": " + why);
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
+        return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < B.end) return fail(ACO_ERR_NOMEM, "workspace smaller than aco_batch_workspace_bytes");
+
+    aco_batch* b = new (std::nothrow) aco_batch();
+    if (!b) return fail(ACO_ERR_NOMEM, "host allocation failed");
+    char* base = static_cast<char*>(d_workspace);
+    b->count = count;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->cols.resize(count);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < count && e == hipSuccess; ++q) {
+        b->cols[q] = aco::host::carve(base + B.inst_off[q], B.inst[q], params[q], false,
+                                      aco::host::tile_for(params[q].n));
+        e = aco::host::upload_and_init(b->cols[q], dist_hosts[q], B.inst[q].base_end, b->stream);
+        b->max_n = std::max(b->max_n, params[q].n);
+        b->max_ld = std::max(b->max_ld, B.inst[q].ld);
+    }
+    b->order.resize(count);
+    for (int q = 0; q < count; ++q) b->order[q] = q;
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int a, int c) { return params[a].n > params[c].n; });
+    std::vector<aco::Colony> launch_cols(count);
+    std::vector<uint32_t> antmap, rowmap;
+    antmap.reserve(B.total_ants);
+    rowmap.reserve(B.total_rows);
+    for (int pos = 0; pos < count; ++pos) {
+        const int q = b->order[pos];
+        launch_cols[pos] = b->cols[q];
+        for (int k = 0; k < params[q].m; ++k) antmap.push_back(((uint32_t)pos << 16) | (uint32_t)k);
+        for (int i = 0; i < params[q].n; ++i) rowmap.push_back(((uint32_t)pos << 16) | (uint32_t)i);
+    }
+    b->total_ants = B.total_ants;
+    b->total_rows = B.total_rows;
+    b->d_cols = reinterpret_cast<aco::Colony*>(base + B.cols_off);
+    b->d_antmap = reinterpret_cast<uint32_t*>(base + B.antmap_off);
+    b->d_rowmap = reinterpret_cast<uint32_t*>(base + B.rowmap_off);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_cols, launch_cols.data(), sizeof(aco::Colony) * count,
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_antmap, antmap.data(), sizeof(uint32_t) * antmap.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_rowmap, rowmap.data(), sizeof(uint32_t) * rowmap.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        const aco_status s = batch_device_fail(b, e, "aco_batch_init");
+        delete b;
+        return s;
+    }
+    *out = b;
+    return ACO_OK;
+}
+
+aco_status aco_batch_run(aco_batch* b, uint32_t iters, int32_t use_graph) {
+    if (aco_status s = batch_usable(b)) return s;
+    if (iters == 0) return ACO_OK;
+    hipError_t e;
+    if (!use_graph) {
+        e = enqueue_iterations(b, iters);
+        if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_run");
+        return ACO_OK;
+    }
+    if (!b->stream)
+        return fail(ACO_ERR_INVALID, "graph capture needs a non-default stream");
+    if (!b->exec || b->graph_iters != iters) {
+        drop_graph(b);
+        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_run: begin capture");
+        const hipError_t enq = enqueue_iterations(b, iters);
+        e = hipStreamEndCapture(b->stream, &b->graph);
+        if (enq != hipSuccess) e = enq;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return batch_device_fail(b, e, "aco_batch_run: capture");
+        }
+        b->graph_iters = iters;
+    }
+    e = hipGraphLaunch(b->exec, b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_run: graph launch");
+    return ACO_OK;
+}
+
+aco_status aco_batch_sync(aco_batch* b) {
+    if (aco_status s = batch_usable(b)) return s;
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_sync");
+    return ACO_OK;
+}
+
+static aco_status batch_instance(aco_batch* b, int32_t q, const aco::Colony** col) {
+    if (aco_status s = batch_usable(b)) return s;
+    if (q < 0 || q >= b->count) return fail(ACO_ERR_INVALID, "instance index out of range");
+    if (aco_status s = aco_batch_sync(b)) return s;
+    *col = &b->cols[q];
+    return ACO_OK;
+}
+
+aco_status aco_batch_read_best(aco_batch* b, int32_t q, uint16_t* best_tour_host,
+                               int64_t* best_len_host) {
+    const aco::Colony* c;
+    if (aco_status s = batch_instance(b, q, &c)) return s;
+    hipError_t e = hipSuccess;
+    if (best_len_host) e = hipMemcpy(best_len_host, c->best_len, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && best_tour_host)
+        e = hipMemcpy(best_tour_host, c->best_tour, ((size_t)c->n + 1) * sizeof(uint16_t),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_read_best");
+    return ACO_OK;
+}
+
+aco_status aco_batch_read_tours(aco_batch* b, int32_t q, uint16_t* tours_host, int64_t* lens_host) {
+    const aco::Colony* c;
+    if (aco_status s = batch_instance(b, q, &c)) return s;
+    hipError_t e = hipSuccess;
+    if (tours_host)
+        e = hipMemcpy2D(tours_host, ((size_t)c->n + 1) * sizeof(uint16_t), c->tours,
+                        (size_t)c->tp * sizeof(uint16_t), ((size_t)c->n + 1) * sizeof(uint16_t),
+                        (size_t)c->m, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && lens_host)
+        e = hipMemcpy(lens_host, c->lens, (size_t)c->m * sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_read_tours");
+    return ACO_OK;
+}
+
+aco_status aco_batch_read_tau(aco_batch* b, int32_t q, float* tau_host) {
+    const aco::Colony* c;
+    if (aco_status s = batch_instance(b, q, &c)) return s;
+    if (!tau_host) return fail(ACO_ERR_INVALID, "tau_host is NULL");
+    const hipError_t e =
+        hipMemcpy2D(tau_host, (size_t)c->n * sizeof(float), c->tau, (size_t)c->ld * sizeof(float),
+                    (size_t)c->n * sizeof(float), (size_t)c->n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_read_tau");
+    return ACO_OK;
+}
+
+aco_status aco_batch_get_iter(aco_batch* b, int32_t q, uint32_t* iter) {
+    const aco::Colony* c;
+    if (aco_status s = batch_instance(b, q, &c)) return s;
+    if (!iter) return fail(ACO_ERR_INVALID, "iter is NULL");
+    const hipError_t e = hipMemcpy(iter, c->iter_dev, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_get_iter");
+    return ACO_OK;
+}
+
+void aco_batch_destroy(aco_batch* b) {
+    if (!b) return;
+    drop_graph(b);
+    delete b;
+}
+
+aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes, int32_t count,
+                        int32_t reps, void* hip_stream, int32_t* chosen, float* ms_tile4,
+                        float* ms_tile8) {
+    aco::host::g_error.clear();
+    if (!sizes || count < 1) return fail(ACO_ERR_INVALID, "need at least one size");
+    if (reps < 1) return fail(ACO_ERR_INVALID, "reps must be >= 1");
+    for (int i = 0; i < count; ++i) {
+        if (sizes[i] < 3 || sizes[i] > aco::kMaxCities)
+            return fail(ACO_ERR_INVALID, "sizes must be in [3, 4096]");
+        if (i > 0 && sizes[i] <= sizes[i - 1])
+            return fail(ACO_ERR_INVALID, "sizes must be strictly increasing");
+    }
+    const aco_params pmax{sizes[count - 1], sizes[count - 1], 1, 2, 0.5f, 1};
+    const aco::host::Layout Lmax = aco::host::make_layout(pmax);
+    if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
+        return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < Lmax.base_end)
+        return fail(ACO_ERR_NOMEM, "workspace smaller than aco_workspace_bytes(largest size, m = n)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    std::vector<int> best(count, 8);
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+        const int n = sizes[i];
+        const aco_params p{n, n, 1, 2, 0.5f, 1};
+        const aco::host::Layout L = aco::host::make_layout(p);
+        const std::vector<int32_t> d = tuning_instance(n);
+        float t_best = 1e30f;
+        for (int tile : {4, 8}) {
+            float* out = tile == 4 ? ms_tile4 : ms_tile8;
+            if (out) out[i] = -1.0f;
+            if (!aco::tile_supported(tile, n)) continue;
+            const aco::Colony col =
+                aco::host::carve(static_cast<char*>(d_workspace), L, p, false, tile);
+            e = aco::host::upload_and_init(col, d.data(), L.base_end, s);
+            if (e == hipSuccess) e = aco::launch_construct(col, 0, s);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && e == hipSuccess; ++r)
+                e = aco::launch_construct(col, (uint32_t)r + 1u, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            ms /= (float)reps;
+            if (out) out[i] = ms;
+            if (ms < t_best) {
+                t_best = ms;
+                best[i] = tile;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return aco::host::device_fail(nullptr, e, "aco_autotune");
+    // Size bucket i covers (sizes[i-1], sizes[i]]; the last bucket runs to 4096.
+    for (int i = 0; i < count; ++i) {
+        const int lo = i == 0 ? 1 : sizes[i - 1] + 1;
+        const int hi = i == count - 1 ? aco::kMaxCities : sizes[i];
+        if (best[i] == 4) {
+            const int top = std::min(hi, aco::kMaxTile4Cities);
+            if (lo <= top) aco::host::set_tile_range(lo, top, 4);
+            if (top < hi) aco::host::set_tile_range(std::max(lo, top + 1), hi, 8);
+        } else {
+            aco::host::set_tile_range(lo, hi, 8);
+        }
+        if (chosen) chosen[i] = best[i];
+    }
+    return ACO_OK;
+}
+
+}  // extern "C"

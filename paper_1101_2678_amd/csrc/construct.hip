@@ -2,15 +2,16 @@
 // data-parallel design of Section III-A: one workgroup per ant, the ant's
 // candidate cities spread over the lanes).
 //
-// Layout of one step (ant at city `cur`, wavefront of 64 lanes):
+// Layout of one step (ant at city `cur`, wavefront of 64 lanes, tile G = 4
+// or 8 cities per lane):
 //   * the choice row of `cur` is streamed with 16-byte loads; in pass p lane l
-//     holds cities 512p + 8l .. 512p + 8l + 7, so one pass reads 2 KB
-//     contiguously and every 64-city block sits in 8 neighbouring lanes;
-//   * visited cities are masked to +0 with a per-lane bit set (bit 8p + e);
-//   * the total T_b of each 64-city block is a balanced pairwise sum: three
-//     levels inside the lane, three DPP levels across the 8 lanes.  That is
-//     exactly the last entry of the 64-wide S64 prefix tree, so every T_b is
-//     bit-identical to the roulette's definition;
+//     holds cities 64Gp + Gl .. 64Gp + Gl + G-1, so one pass reads 256 G bytes
+//     contiguously and every 64-city block sits in 64/G neighbouring lanes;
+//   * visited cities are masked to +0 with a per-lane bit set (bit Gp + e);
+//   * the total T_b of each 64-city block is a balanced pairwise sum: log2 G
+//     levels inside the lane, log2(64/G) DPP levels across the lanes.  That
+//     is exactly the last entry of the 64-wide S64 prefix tree, so every T_b
+//     is bit-identical to the roulette's definition whatever G is;
 //   * T_b move to lane b through LDS and are scanned with S64 (DPP), giving
 //     the block offsets E_b and the total;
 //   * a block can hold the chosen city only if fl(E_b + T_b (1 + 2^-20)) >
@@ -19,7 +20,8 @@
 //     test can be skipped without changing the result;
 //   * surviving blocks are rescanned one element per lane with the exact S64
 //     tree, in block order, until the first feasible prefix above the target.
-// Random numbers: Philox draw (seed, iter, ant, step) on the scalar unit.
+// Random numbers: Philox draws (seed, iter, ant, step), 64 steps at a time on
+// the vector unit.
 #include "aco_device.hpp"
 #include "aco_state.hpp"
 
@@ -28,16 +30,27 @@ namespace {
 
 constexpr float kBlockSlack = 1.00000095367431640625f;  // 1 + 2^-20
 
-// Per-lane feasibility bits: bit 8p + e <=> city 512p + 8 lane + e is < n and
-// not yet visited.
-template <int P>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Cities per lane per pass (G), and what follows from it.
+template <int G>
+struct Tile {
+    static_assert(G == 4 || G == 8, "tile must be 4 or 8 cities per lane");
+    static constexpr int kPass = 64 * G;          // cities per pass
+    static constexpr int kLanesPerBlock = 64 / G; // lanes holding one 64-city block
+    static constexpr int kMaxPasses = 64 / G;     // lane bit set holds 64 bits
+};
+
+// Per-lane feasibility bits: bit G p + e <=> city 64 G p + G lane + e is < n
+// and not yet visited.  Passes at or beyond np stay empty.
+template <int G, int P>
 __device__ __forceinline__ uint64_t initial_lane_bits(int n, int lane) {
     uint64_t bits = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < kCitiesPerLane; ++e)
-            if (p * kPassCities + lane * kCitiesPerLane + e < n) bits |= 1ull << (p * 8 + e);
+        for (int e = 0; e < G; ++e)
+            if (p * Tile<G>::kPass + lane * G + e < n) bits |= 1ull << (p * G + e);
     return bits;
 }
 
@@ -50,13 +63,14 @@ __device__ __forceinline__ uint64_t initial_block_bits(int n, int b) {
 }
 
 // Clears city j in both tabu representations (called with j uniform).
+template <int G>
 __device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& lane_bits,
                                              uint64_t* s_vis) {
     if (lane == 0)
         __hip_atomic_fetch_or(&s_vis[j >> 6], 1ull << (j & 63), __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_WORKGROUP);
-    const int owner = (j & (kPassCities - 1)) >> 3;
-    const int bit = ((j / kPassCities) << 3) + (j & 7);
+    const int owner = (j % Tile<G>::kPass) / G;
+    const int bit = (j / Tile<G>::kPass) * G + (j % G);
     if (lane == owner) lane_bits &= ~(1ull << bit);
 }
 
@@ -69,8 +83,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int
                                              0x00020000);
 }
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
 // Sign-extended bit `e` of `bits` (0 or all ones).  Written as v_bfe_i32 so
 // the masking of one city costs two VALU operations (extract, and).
 template <int E>
@@ -80,65 +92,92 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t bits) {
     return m;
 }
 
+template <int E0>
+__device__ __forceinline__ void mask4(u32x4& v, uint32_t bits) {
+    v.x &= bit_mask<E0 + 0>(bits);
+    v.y &= bit_mask<E0 + 1>(bits);
+    v.z &= bit_mask<E0 + 2>(bits);
+    v.w &= bit_mask<E0 + 3>(bits);
+}
+
+__device__ __forceinline__ float pair_sum4(const u32x4& v) {
+    return (__uint_as_float(v.x) + __uint_as_float(v.y)) +
+           (__uint_as_float(v.z) + __uint_as_float(v.w));
+}
+
+// Balanced pairwise sum over groups of LANES consecutive lanes (LANES = 8 or
+// 16, inside one 16-lane DPP row); the last lane of each group ends with it.
+template <int LANES>
+__device__ __forceinline__ float group_pairwise(float x) {
+    x = x + dpp_move<0x111, 0xF>(x);
+    x = x + dpp_move<0x112, 0xF>(x);
+    x = x + dpp_move<0x114, 0xF>(x);
+    if (LANES == 16) x = x + dpp_move<0x118, 0xF>(x);
+    return x;
+}
+
 // Stages the masked weights of block `b` into s_w (city 64b + t at
-// s_w[64 (b mod 8) + t]).  The block lives in pass b/8, lanes 8 (b mod 8) ..
-// 8 (b mod 8) + 7; the pass index is wave-uniform but not a compile-time
-// constant, so each pass has its own branch, and the stores are opaque to the
-// optimiser so that it cannot merge the branches into per-register selects.
-template <int P>
+// s_w[64 (b mod G) + t]).  The block lives in pass b/G, lanes
+// (64/G)(b mod G) .. (64/G)(b mod G + 1) - 1; the pass index is wave-uniform
+// but not a compile-time constant, so each pass has its own branch, and the
+// stores are opaque to the optimiser so that it cannot merge the branches
+// into per-register selects.
+template <int G, int P>
 __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&wb)[P], int b,
                                             float* s_w, int lane) {
-    const int pb = b >> 3;
-    if ((lane >> 3) != (b & 7)) return;
-    const uint32_t addr = (uint32_t)(uintptr_t)(s_w + lane * kCitiesPerLane);
+    const int pb = b / G;
+    if (lane / Tile<G>::kLanesPerBlock != (b % G)) return;
+    const uint32_t addr = (uint32_t)(uintptr_t)(s_w + lane * G);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (p == pb) {
-            asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:16"
-                         :
-                         : "v"(addr), "v"(wa[p]), "v"(wb[p])
-                         : "memory");
+            if (G == 8)
+                asm volatile("ds_write_b128 %0, %1\n\tds_write_b128 %0, %2 offset:16"
+                             :
+                             : "v"(addr), "v"(wa[p]), "v"(wb[p])
+                             : "memory");
+            else
+                asm volatile("ds_write_b128 %0, %1" : : "v"(addr), "v"(wa[p]) : "memory");
         }
     }
 }
 
-// One R64 roulette draw over `row` (ld-padded, zero beyond n).
-// Returns the chosen city, or -1 if no city is feasible.  Wave-uniform.
+// One R64 roulette draw over `row` (ld-padded, zero beyond n), with np <= P
+// passes in use (np == P when GUARD is false).  Returns the chosen city, or
+// -1 if no city is feasible.  Wave-uniform.
 // The masked weights stay in registers; the pass holding a candidate block
-// is staged into LDS (city j at s_w[j]) only when that block is scanned.  The
-// workgroup is one wavefront: its LDS operations execute in program order,
-// and every LDS access below uses a lane-dependent index, so the compiler
-// keeps the order.
-template <int P>
-__device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, uint64_t lane_bits,
-                                        const uint64_t* s_vis, float* s_T, float* s_w, float u,
-                                        int lane) {
+// is staged into LDS only when that block is scanned.  The workgroup is one
+// wavefront: its LDS operations execute in program order, and every LDS
+// access below uses a lane-dependent index, so the compiler keeps the order.
+template <int G, int P, bool GUARD>
+__device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
+                                        uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
+                                        float* s_w, float u, int lane) {
+    constexpr int LPB = Tile<G>::kLanesPerBlock;
     const int nb = (n + 63) >> 6;
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
     u32x4 wa[P], wb[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int off = (p * kPassCities + lane * kCitiesPerLane) * 4;
+        if (GUARD && p >= np) break;
+        const int off = (p * Tile<G>::kPass + lane * G) * 4;
         wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        if (G == 8) wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const uint32_t bits = (uint32_t)(lane_bits >> (p * 8));
-        wa[p].x &= bit_mask<0>(bits);
-        wa[p].y &= bit_mask<1>(bits);
-        wa[p].z &= bit_mask<2>(bits);
-        wa[p].w &= bit_mask<3>(bits);
-        wb[p].x &= bit_mask<4>(bits);
-        wb[p].y &= bit_mask<5>(bits);
-        wb[p].z &= bit_mask<6>(bits);
-        wb[p].w &= bit_mask<7>(bits);
-        float t = ((__uint_as_float(wa[p].x) + __uint_as_float(wa[p].y)) +
-                   (__uint_as_float(wa[p].z) + __uint_as_float(wa[p].w))) +
-                  ((__uint_as_float(wb[p].x) + __uint_as_float(wb[p].y)) +
-                   (__uint_as_float(wb[p].z) + __uint_as_float(wb[p].w)));
-        t = octet_pairwise(t);
-        if ((lane & 7) == 7) s_T[p * 8 + (lane >> 3)] = t;
+        if (GUARD && p >= np) break;
+        const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
+        mask4<0>(wa[p], bits);
+        float t;
+        if (G == 8) {
+            mask4<4>(wb[p], bits);
+            t = pair_sum4(wa[p]) + pair_sum4(wb[p]);
+        } else {
+            t = pair_sum4(wa[p]);
+        }
+        t = group_pairwise<LPB>(t);
+        if ((lane % LPB) == LPB - 1) s_T[p * G + lane / LPB] = t;
     }
     const float T = s_T[lane];
     const float I = s64_scan(T);
@@ -150,9 +189,9 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, ui
     while (cand) {
         const int b = __builtin_ctzll(cand);
         cand &= cand - 1;
-        stage_block<P>(wa, wb, b, s_w, lane);
+        stage_block<G, P>(wa, wb, b, s_w, lane);
         const uint64_t vis = s_vis[b];
-        const float w = s_w[(b & 7) * 64 + lane];
+        const float w = s_w[(b % G) * 64 + lane];
         const bool feasible = ((vis >> lane) & 1ull) == 0ull;
         const float s = s64_scan(w);
         const float eb = read_lane(E, b);
@@ -174,26 +213,32 @@ __device__ __forceinline__ float draws64(PhiloxKey key, uint32_t iter, uint32_t 
     return uniform24(draw(key, iter, ant, (uint32_t)(s0 + lane)));
 }
 
-template <int P>
-__global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
-    extern __shared__ uint16_t s_tour[];
-    __shared__ __align__(16) float s_w[kPassCities];
-    __shared__ uint64_t s_vis[64];
-    __shared__ float s_T[64];
+// LDS a construction workgroup needs besides the tour.
+struct AntShared {
+    float w[512];       // staged candidate block weights (64 G floats)
+    uint64_t vis[64];   // visited bits per 64-city block
+    float T[64];        // block totals in block order
+};
+
+// The whole tour of ant k of colony c in iteration `iter`: placement, n - 1
+// roulette steps, then length, deposit, tour and neighbour tables.
+template <int G, int P, bool GUARD>
+__device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t iter,
+                                              uint16_t* s_tour, AntShared& sh) {
     const int lane = threadIdx.x;
-    const int k = blockIdx.x;
     const int n = c.n;
+    const int np = GUARD ? (n + Tile<G>::kPass - 1) / Tile<G>::kPass : P;
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
-    s_vis[lane] = initial_block_bits(n, lane);
-    s_T[lane] = 0.0f;
-    uint64_t lane_bits = initial_lane_bits<P>(n, lane);
+    sh.vis[lane] = initial_block_bits(n, lane);
+    sh.T[lane] = 0.0f;
+    uint64_t lane_bits = initial_lane_bits<G, P>(n, lane);
     __syncthreads();
 
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
     if (lane == 0) s_tour[0] = (uint16_t)cur;
-    mark_visited(cur, lane, lane_bits, s_vis);
+    mark_visited<G>(cur, lane, lane_bits, sh.vis);
 
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
@@ -201,12 +246,12 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
         if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const float* row = c.choice + (size_t)cur * c.ld;
-        int j = r64_pick<P>(row, n, lane_bits, s_vis, s_T, s_w, u, lane);
+        int j = r64_pick<G, P, GUARD>(row, n, np, lane_bits, sh.vis, sh.T, sh.w, u, lane);
         // At every step n - step >= 1 cities are unvisited, so j >= 0; the
         // clamp only keeps the LDS indices in range should that ever break.
         j = j < 0 ? 0 : j;
         if (lane == 0) s_tour[step] = (uint16_t)j;
-        mark_visited(j, lane, lane_bits, s_vis);
+        mark_visited<G>(j, lane, lane_bits, sh.vis);
         cur = j;
     }
     __syncthreads();
@@ -231,13 +276,34 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     }
 }
 
-template <int P>
+template <int G, int P>
+__global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
+    extern __shared__ uint16_t s_tour[];
+    __shared__ __align__(16) AntShared sh;
+    construct_ant<G, P, false>(c, blockIdx.x, iter, s_tour, sh);
+}
+
+// Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
+// cols[antmap[g] >> 16] in that colony's current iteration (*iter_dev).  Each
+// colony carries its own tile; the pass count is read at run time (GUARD).
+__global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict__ cols,
+                                                        const uint32_t* __restrict__ antmap) {
+    extern __shared__ uint16_t s_tour[];
+    __shared__ __align__(16) AntShared sh;
+    const uint32_t e = antmap[blockIdx.x];
+    const Colony c = cols[e >> 16];
+    const uint32_t iter = *c.iter_dev;
+    if (c.tile == 4)
+        construct_ant<4, 4, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+    else
+        construct_ant<8, 8, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+}
+
+template <int G, int P>
 __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, int n,
                                                      const uint8_t* feasible, const float* us,
                                                      int32_t* out) {
-    __shared__ __align__(16) float s_w[kPassCities];
-    __shared__ uint64_t s_vis[64];
-    __shared__ float s_T[64];
+    __shared__ __align__(16) AntShared sh;
     const int lane = threadIdx.x;
     const int q = blockIdx.x;
     const uint8_t* f = feasible + (size_t)q * n;
@@ -246,92 +312,96 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
         const int j = lane * 64 + t;
         if (j < n && f[j]) vis &= ~(1ull << t);
     }
-    s_vis[lane] = vis;
-    s_T[lane] = 0.0f;
+    sh.vis[lane] = vis;
+    sh.T[lane] = 0.0f;
     uint64_t lane_bits = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < kCitiesPerLane; ++e) {
-            const int j = p * kPassCities + lane * kCitiesPerLane + e;
-            if (j < n && f[j]) lane_bits |= 1ull << (p * 8 + e);
+        for (int e = 0; e < G; ++e) {
+            const int j = p * Tile<G>::kPass + lane * G + e;
+            if (j < n && f[j]) lane_bits |= 1ull << (p * G + e);
         }
     __syncthreads();
-    const int j =
-        r64_pick<P>(rows + (size_t)q * ld, n, lane_bits, s_vis, s_T, s_w, us[q], lane);
+    const int j = r64_pick<G, P, false>(rows + (size_t)q * ld, n, P, lane_bits, sh.vis, sh.T,
+                                        sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
 
-template <int P>
-hipError_t launch_construct_p(const Colony& c, uint32_t iter, hipStream_t s) {
-    const size_t lds = ((size_t)(c.n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
-    hipLaunchKernelGGL(k_construct<P>, dim3(c.m), dim3(64), lds, s, c, iter);
-    return hipGetLastError();
-}
+size_t tour_lds_bytes(int n) { return ((size_t)(n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15; }
 
-template <int P>
-hipError_t launch_select_p(int n, int count, const float* rows, const uint8_t* feasible,
-                           const float* u, int32_t* out, hipStream_t s) {
-    const int ld = (n + 63) & ~63;
-    hipLaunchKernelGGL(k_test_select<P>, dim3(count), dim3(64), 0, s, rows, ld, n, feasible, u,
-                       out);
-    return hipGetLastError();
-}
-
-template <int P>
-int occupancy_p(const Colony& c) {
-    int blocks = 0;
-    const size_t lds = ((size_t)(c.n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_construct<P>, 64, lds) !=
-        hipSuccess)
-        return -1;
-    return blocks;
+// Calls f.template operator()<G, P>() for the tile and pass count of n.
+template <typename F>
+hipError_t dispatch_tile(int tile, int n, F&& f) {
+    if (tile == 4) {
+        switch ((n + 255) / 256) {
+            case 1: return f.template operator()<4, 1>();
+            case 2: return f.template operator()<4, 2>();
+            case 3: return f.template operator()<4, 3>();
+            case 4: return f.template operator()<4, 4>();
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch ((n + 511) / 512) {
+        case 1: return f.template operator()<8, 1>();
+        case 2: return f.template operator()<8, 2>();
+        case 3: return f.template operator()<8, 3>();
+        case 4: return f.template operator()<8, 4>();
+        case 5: return f.template operator()<8, 5>();
+        case 6: return f.template operator()<8, 6>();
+        case 7: return f.template operator()<8, 7>();
+        case 8: return f.template operator()<8, 8>();
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
+bool tile_supported(int tile, int n) {
+    if (tile == 8) return n >= 1 && n <= kMaxCities;
+    if (tile == 4) return n >= 1 && n <= 1024;
+    return false;
+}
+
 int construct_occupancy(const Colony& c) {
-    switch ((c.n + kPassCities - 1) / kPassCities) {
-        case 1: return occupancy_p<1>(c);
-        case 2: return occupancy_p<2>(c);
-        case 3: return occupancy_p<3>(c);
-        case 4: return occupancy_p<4>(c);
-        case 5: return occupancy_p<5>(c);
-        case 6: return occupancy_p<6>(c);
-        case 7: return occupancy_p<7>(c);
-        case 8: return occupancy_p<8>(c);
-        default: return -1;
-    }
+    int blocks = -1;
+    (void)dispatch_tile(c.tile, c.n, [&]<int G, int P>() {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_construct<G, P>, 64,
+                                                         tour_lds_bytes(c.n)) != hipSuccess)
+            blocks = -1;
+        return hipSuccess;
+    });
+    return blocks;
 }
 
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s) {
-    switch ((c.n + kPassCities - 1) / kPassCities) {
-        case 1: return launch_construct_p<1>(c, iter, s);
-        case 2: return launch_construct_p<2>(c, iter, s);
-        case 3: return launch_construct_p<3>(c, iter, s);
-        case 4: return launch_construct_p<4>(c, iter, s);
-        case 5: return launch_construct_p<5>(c, iter, s);
-        case 6: return launch_construct_p<6>(c, iter, s);
-        case 7: return launch_construct_p<7>(c, iter, s);
-        case 8: return launch_construct_p<8>(c, iter, s);
-        default: return hipErrorInvalidValue;
-    }
+    if (!tile_supported(c.tile, c.n)) return hipErrorInvalidValue;
+    return dispatch_tile(c.tile, c.n, [&]<int G, int P>() {
+        hipLaunchKernelGGL((k_construct<G, P>), dim3(c.m), dim3(64), tour_lds_bytes(c.n), s, c,
+                           iter);
+        return hipGetLastError();
+    });
 }
 
-hipError_t launch_test_select(int n, int count, const float* rows, const uint8_t* feasible,
-                              const float* u, int32_t* out, hipStream_t s) {
+hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
+                                  int max_n, hipStream_t s) {
+    if (total_ants <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_construct_batch, dim3(total_ants), dim3(64), tour_lds_bytes(max_n), s,
+                       cols, antmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_test_select(int tile, int n, int count, const float* rows,
+                              const uint8_t* feasible, const float* u, int32_t* out,
+                              hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    switch ((n + kPassCities - 1) / kPassCities) {
-        case 1: return launch_select_p<1>(n, count, rows, feasible, u, out, s);
-        case 2: return launch_select_p<2>(n, count, rows, feasible, u, out, s);
-        case 3: return launch_select_p<3>(n, count, rows, feasible, u, out, s);
-        case 4: return launch_select_p<4>(n, count, rows, feasible, u, out, s);
-        case 5: return launch_select_p<5>(n, count, rows, feasible, u, out, s);
-        case 6: return launch_select_p<6>(n, count, rows, feasible, u, out, s);
-        case 7: return launch_select_p<7>(n, count, rows, feasible, u, out, s);
-        case 8: return launch_select_p<8>(n, count, rows, feasible, u, out, s);
-        default: return hipErrorInvalidValue;
-    }
+    if (!tile_supported(tile, n)) return hipErrorInvalidValue;
+    const int ld = (n + 63) & ~63;
+    return dispatch_tile(tile, n, [&]<int G, int P>() {
+        hipLaunchKernelGGL((k_test_select<G, P>), dim3(count), dim3(64), 0, s, rows, ld, n,
+                           feasible, u, out);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace aco

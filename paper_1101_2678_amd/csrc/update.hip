@@ -36,9 +36,8 @@ __device__ __forceinline__ void apply_cell(float& tau, float& choice, int32_t d,
     choice = choice_of(tau, heur_of(d, beta), alpha);
 }
 
-__global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
-    extern __shared__ double s_D[];  // ld binary64 accumulators
-    const int i = blockIdx.x;
+// Row i of the gather update (tid in [0, kRowThreads)).
+__device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) {
     const int tid = threadIdx.x;
     for (int j = tid; j < c.ld; j += kRowThreads) s_D[j] = 0.0;
     __syncthreads();
@@ -65,6 +64,21 @@ __global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
         trow[q] = t;
         crow[q] = ch;
     }
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
+    extern __shared__ double s_D[];  // ld binary64 accumulators
+    gather_row(c, blockIdx.x, s_D);
+}
+
+// Batched gather: workgroup g updates row (rowmap[g] & 0xffff) of colony
+// cols[rowmap[g] >> 16].
+__global__ __launch_bounds__(kRowThreads) void k_update_gather_batch(
+    const Colony* __restrict__ cols, const uint32_t* __restrict__ rowmap) {
+    extern __shared__ double s_D[];
+    const uint32_t e = rowmap[blockIdx.x];
+    const Colony c = cols[e >> 16];
+    gather_row(c, (int)(e & 0xffffu), s_D);
 }
 
 // grid (ceil(n / 256), m): thread (s, k) deposits edge (tour_k[s], tour_k[s+1]).
@@ -207,7 +221,7 @@ __global__ __launch_bounds__(256) void k_refresh_choice(Colony c) {
 // Best-so-far: the shortest tour of this iteration (lowest ant index among
 // equals) replaces the stored one only if strictly shorter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_best(Colony c) {
+__device__ __forceinline__ void best_of(const Colony& c, bool advance_iter) {
     __shared__ unsigned long long part[16];
     __shared__ unsigned long long s_win;
     const int tid = threadIdx.x;
@@ -226,11 +240,22 @@ __global__ __launch_bounds__(1024) void k_best(Colony c) {
     const long long len = (long long)(s_win >> 16);
     const int k = (int)(s_win & 0xffffu);
     const long long prev = *c.best_len;
-    if (len >= prev) return;
-    const uint16_t* src = c.tours + (size_t)k * c.tp;
-    for (int s = tid; s <= c.n; s += 1024) c.best_tour[s] = src[s];
-    __syncthreads();
-    if (tid == 0) *c.best_len = len;
+    if (len < prev) {
+        const uint16_t* src = c.tours + (size_t)k * c.tp;
+        for (int s = tid; s <= c.n; s += 1024) c.best_tour[s] = src[s];
+        __syncthreads();
+        if (tid == 0) *c.best_len = len;
+    }
+    // The batched path keeps each colony's iteration counter on the device,
+    // so that a captured sequence of launches advances when replayed.
+    if (advance_iter && tid == 0) *c.iter_dev += 1u;
+}
+
+__global__ __launch_bounds__(1024) void k_best(Colony c) { best_of(c, false); }
+
+__global__ __launch_bounds__(1024) void k_best_batch(const Colony* __restrict__ cols) {
+    const Colony c = cols[blockIdx.x];
+    best_of(c, true);
 }
 
 dim3 cell_grid(const Colony& c) { return dim3((c.ld / 4 + 255) / 256, c.n); }
@@ -263,6 +288,20 @@ hipError_t launch_refresh_choice(const Colony& c, hipStream_t s) {
 
 hipError_t launch_best(const Colony& c, hipStream_t s) {
     hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_batch(const Colony* cols, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap, int total_rows,
+                                      int max_ld, hipStream_t s) {
+    if (total_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_gather_batch, dim3(total_rows), dim3(kRowThreads),
+                       (size_t)max_ld * sizeof(double), s, cols, rowmap);
     return hipGetLastError();
 }
 

@@ -111,10 +111,66 @@ def test_calls_on_null_context(aco):
 
 
 def test_probe_and_select_validation(aco):
-    assert aco.lib.aco_test_select(0, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
-    assert aco.lib.aco_test_select(4097, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
-    assert aco.lib.aco_test_select(10, -1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
-    assert aco.lib.aco_test_select(10, 1, None, 16, 16, 16, None) == aco.ACO_ERR_INVALID
-    assert aco.lib.aco_test_select(10, 0, None, None, None, None, None) == aco.ACO_OK
+    sel = aco.lib.aco_test_select
+    assert sel(8, 0, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 4097, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 10, -1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 10, 1, None, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert sel(4, 1025, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID  # tile 4: n <= 1024
+    assert sel(6, 100, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 10, 0, None, None, None, None, None) == aco.ACO_OK
     assert aco.lib.aco_probe_copy(16, 16, 15, None) == aco.ACO_ERR_INVALID
     assert aco.lib.aco_probe_read(16, 32, -1, 16, None) == aco.ACO_ERR_INVALID
+    rows = aco.lib.aco_probe_rows
+    assert rows(16, 0, 64, 64, 1, 1, 16, None) == aco.ACO_ERR_INVALID
+    assert rows(16, 10, 60, 64, 1, 1, 16, None) == aco.ACO_ERR_INVALID  # ld < row_len
+    assert rows(16, 10, 66, 64, 1, 1, 16, None) == aco.ACO_ERR_INVALID  # ld % 4
+    assert rows(16, 10, 4160, 4097, 1, 1, 16, None) == aco.ACO_ERR_INVALID
+
+
+def test_tile_table(aco):
+    assert aco.get_tile(2400) == 8
+    with pytest.raises(aco.AcoError):
+        aco.set_tile(900, 1100, 4)  # tile 4 stops at n = 1024
+    with pytest.raises(aco.AcoError):
+        aco.set_tile(10, 5, 8)
+    with pytest.raises(aco.AcoError):
+        aco.set_tile(10, 20, 5)
+    aco.set_tile(100, 200, 4)
+    assert [aco.get_tile(n) for n in (99, 100, 200, 201)] == [8, 4, 4, 8]
+    aco.set_tile(1, 4096, 8)
+    assert aco.get_tile(150) == 8
+
+
+def test_batch_workspace_and_validation(aco):
+    P = aco.Params
+    arr = (P * 3)(P(100, 100, 1, 2, 0.5, 1), P(50, 20, 1, 2, 0.5, 2), P(700, 700, 1, 2, 0.5, 3))
+    total = aco.lib.aco_batch_workspace_bytes(3, arr)
+    single = sum(aco.lib.aco_workspace_bytes(ctypes.byref(arr[q]), 0) for q in range(3))
+    assert total >= single + 4 * (100 + 20 + 700) + 4 * (100 + 50 + 700)
+    bad = (P * 2)(P(100, 100, 1, 2, 0.5, 1), P(2, 20, 1, 2, 0.5, 2))
+    assert aco.lib.aco_batch_workspace_bytes(2, bad) == 0
+    assert aco.lib.aco_batch_workspace_bytes(0, arr) == 0
+    b = ctypes.c_void_p()
+    _, d = tsp_inputs.instance(10, "uniform", side=1000, seed=1)
+    asym = d.copy()
+    asym[1, 2] += 1
+    one = (P * 1)(P(10, 5, 1, 2, 0.5, 1))
+    ptrs = (ctypes.c_void_p * 1)(asym.ctypes.data)
+    assert aco.lib.aco_batch_init(ctypes.byref(b), 1, one, ptrs, 0x100000, 1 << 40,
+                                  None) == aco.ACO_ERR_INVALID
+    assert b"instance 0" in aco.lib.aco_last_error()
+    assert aco.lib.aco_batch_run(None, 1, 0) == aco.ACO_ERR_INVALID
+    aco.lib.aco_batch_destroy(None)
+
+
+def test_autotune_validation(aco):
+    sizes = (ctypes.c_int32 * 2)(200, 100)
+    assert aco.lib.aco_autotune(0x100000, 1 << 40, sizes, 2, 1, None, None, None,
+                                None) == aco.ACO_ERR_INVALID  # not increasing
+    sizes = (ctypes.c_int32 * 1)(2)
+    assert aco.lib.aco_autotune(0x100000, 1 << 40, sizes, 1, 1, None, None, None,
+                                None) == aco.ACO_ERR_INVALID
+    sizes = (ctypes.c_int32 * 1)(100)
+    assert aco.lib.aco_autotune(0x100000, 10, sizes, 1, 1, None, None, None,
+                                None) == aco.ACO_ERR_NOMEM

@@ -1,0 +1,170 @@
+"""GPU: construction tiles, batches and graph replays.
+
+Every instance must compute exactly what it computes alone and what the
+oracle computes, whatever tile (cities per lane) the construction kernel
+uses, whatever batch it runs in, and whether the batch's launches run
+directly or as replays of a captured HIP graph.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import tsp_inputs
+from gpu_helpers import ORACLE_THREADS, assert_same_f32, compare_run, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1101_2678_amd import aco
+
+    yield
+    aco.set_tile(1, 4096, 8)  # leave the default table for later tests
+
+
+@pytest.fixture
+def tile4():
+    from paper_1101_2678_amd import aco
+
+    aco.set_tile(1, 1024, 4)
+    yield
+    aco.set_tile(1, 4096, 8)
+
+
+@pytest.mark.parametrize("n", [1, 3, 63, 64, 65, 255, 256, 257, 700, 1024])
+def test_select_tile4_adversarial(n):
+    import torch
+    from paper_1101_2678_amd import aco
+    from test_gpu_parity import _adversarial_rows
+
+    rng = np.random.default_rng(4000 + n)
+    rows, feas, u = _adversarial_rows(n, 2000, rng)
+    args = (torch.from_numpy(rows).cuda(), torch.from_numpy(feas).cuda(), torch.from_numpy(u).cuda())
+    got4 = aco.test_select(*args, tile=4).cpu().numpy()
+    got8 = aco.test_select(*args, tile=8).cpu().numpy()
+    want = oracle.r64_select_batch(rows, feas, u)
+    assert (got4 == want).all() and (got8 == want).all()
+
+
+@pytest.mark.parametrize("n,m,alpha,beta,rho", [
+    (3, 5, 1, 2, 0.5), (100, 100, 1, 2, 0.5), (257, 40, 2, 3, 0.3), (700, 60, 1, 2, 0.5),
+    (1024, 50, 0, 2, 0.9),
+])
+def test_tile4_parity(tile4, n, m, alpha, beta, rho):
+    from paper_1101_2678_amd import aco
+
+    assert aco.get_tile(n) == 4
+    _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=n + 3)
+    compare_run(d, m, alpha, beta, rho, seed=n, iters=3, kinds=("gather",))
+
+
+def _batch_case():
+    """Uneven instances: n from 3 to 2048, varied m, alpha, beta, rho, seed."""
+    spec = [(700, 700, 1, 2, 0.5, 11), (3, 4, 1, 2, 0.5, 12), (64, 64, 1, 2, 0.5, 13),
+            (65, 30, 2, 1, 0.3, 14), (1000, 200, 1, 2, 0.5, 15), (17, 90, 0, 0, 0.5, 16),
+            (2048, 64, 1, 2, 0.2, 17), (513, 513, 1, 3, 0.9, 18), (250, 250, 1, 2, 1.0, 19),
+            (129, 1, 1, 2, 0.5, 20)]
+    dists, params = [], []
+    for (n, m, a, b, r, s) in spec:
+        layout = "cluster" if s % 2 else "uniform"
+        _, d = tsp_inputs.instance(n, layout, side=1_000_000, seed=s)
+        dists.append(d)
+        params.append(dict(m=m, alpha=a, beta=b, rho=r, seed=s))
+    return dists, params
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("tiles", ["8", "mixed"])
+def test_batch_matches_single(graph, tiles):
+    from paper_1101_2678_amd import aco
+    from paper_1101_2678_amd.aco import Batch, Colony
+
+    if tiles == "mixed":
+        aco.set_tile(1, 300, 4)
+    try:
+        dists, params = _batch_case()
+        iters = 4
+        log(f"  batch graph={graph} tiles={tiles}")
+        b = Batch(dists, params)
+        b.run(2, graph=graph)
+        b.run(2, graph=graph)
+        b.sync()
+        for q, (d, p) in enumerate(zip(dists, params)):
+            c = Colony(d, p["m"], p["alpha"], p["beta"], p["rho"], p["seed"], atomic=False)
+            c.solve(iters, "gather")
+            ct, cl = c.tours()
+            bt, bl = b.tours(q)
+            assert (ct == bt).all() and (cl == bl).all(), f"instance {q}: tours differ"
+            assert_same_f32(b.tau(q), c.tau(), f"instance {q} tau")
+            assert b.best(q)[1] == c.best()[1]
+            assert (b.best(q)[0] == c.best()[0]).all()
+            assert b.iteration(q) == iters
+            c.close()
+        b.close()
+    finally:
+        aco.set_tile(1, 4096, 8)
+
+
+def test_batch_against_oracle():
+    """A small batch checked directly against the oracle, instance by instance."""
+    from paper_1101_2678_amd.aco import Batch
+
+    dists, params = [], []
+    for n, m, s in [(30, 30, 1), (5, 7, 2), (130, 50, 3)]:
+        _, d = tsp_inputs.instance(n, "uniform", side=10_000, seed=s)
+        dists.append(d)
+        params.append(dict(m=m, alpha=1, beta=2, rho=0.5, seed=s))
+    b = Batch(dists, params)
+    b.run(3, graph=True)
+    b.sync()
+    for q, (d, p) in enumerate(zip(dists, params)):
+        st = oracle.solve(d, p["m"], 1, 2, 0.5, p["seed"], 3, threads=ORACLE_THREADS)
+        assert_same_f32(b.tau(q), st.tau, f"instance {q} tau vs oracle")
+        assert b.best(q)[1] == st.best_len
+    b.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    """Replays of one captured graph, with other launches and host syncs in
+    between, advance exactly like eager launches."""
+    import torch
+    from paper_1101_2678_amd.aco import Batch
+
+    dists, params = _batch_case()
+    g = Batch(dists, params)
+    e = Batch(dists, params)
+    for r in range(4):
+        g.run(1, graph=True)
+        x = torch.randn(1 << 20, device="cuda")  # unrelated eager work
+        torch.cuda.synchronize()
+        _ = float(x.sum())
+        e.run(1, graph=False)
+        g.sync()
+        e.sync()
+        for q in range(len(dists)):
+            assert_same_f32(g.tau(q), e.tau(q), f"replay {r} instance {q}")
+            assert g.iteration(q) == e.iteration(q) == r + 1
+    g.close()
+    e.close()
+
+
+def test_autotune_sets_table_and_keeps_results():
+    from paper_1101_2678_amd import aco
+
+    try:
+        chosen, ms4, ms8 = aco.autotune([128, 512, 1024, 2400], reps=2)
+        log(f"  autotune chosen={chosen.tolist()} ms4={ms4.tolist()} ms8={ms8.tolist()}")
+        assert set(chosen.tolist()) <= {4, 8}
+        assert ms4[-1] == -1.0 and (ms8 > 0).all()
+        assert aco.get_tile(2400) == 8 and aco.get_tile(4096) == 8
+        _, d = tsp_inputs.instance(300, "uniform", side=1_000_000, seed=9)
+        compare_run(d, 80, 1, 2, 0.5, 9, 2, kinds=("gather",))
+    finally:
+        aco.set_tile(1, 4096, 8)
