@@ -172,12 +172,134 @@ def probe_bandwidth(torch, aco, n: int, m: int):
     return {k: (round(v, 1) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+def bench_batch(args, torch, aco):
+    """256 independent instances, n = round(exp(U(ln 50, ln 1000))), m = n,
+    uniform cities, alpha 1, beta 2, rho 0.5, 25 iterations each, tiles from
+    the autotuner; the batch (one graph replay of 25 iterations x 3 launches)
+    against the same set run one instance per launch on one stream."""
+    count, iters = 256, 25
+    sizes = tsp_inputs.log_uniform_sizes(count, 50, 1000, seed=4)
+    dists = [tsp_inputs.instance(int(n), "uniform", side=1_000_000, seed=q + 1)[1]
+             for q, n in enumerate(sizes)]
+    params = [dict(m=int(n), alpha=ALPHA, beta=BETA, rho=RHO, seed=q + 1)
+              for q, n in enumerate(sizes)]
+    chosen, ms4, ms8 = aco.autotune([64, 128, 256, 512, 1024], reps=3)
+    log(f"bench batch: autotune chosen tiles {chosen.tolist()} (ms tile4 {ms4.tolist()}, "
+        f"tile8 {ms8.tolist()})")
+    stream = torch.cuda.Stream()
+    b = aco.Batch(dists, params, stream=stream)
+    b.run(iters, graph=True)  # captures the graph and runs iterations 0..24
+    b.sync()
+    t0 = time.perf_counter()
+    b.run(iters, graph=True)  # replays it: iterations 25..49
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    cols = [aco.Colony(d, p["m"], ALPHA, BETA, RHO, p["seed"], atomic=False, stream=stream)
+            for d, p in zip(dists, params)]
+    for c in cols:
+        for it in range(2):
+            c.construct(it)
+            c.update("gather")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in cols:
+        for it in range(2, 2 + iters):
+            c.construct(it)
+            c.update("gather")
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    ant_steps = int(sum(int(n) * (int(n) - 1) for n in sizes)) * iters
+    rec = {
+        "metric": "batched solves/s (25 AS iterations per solve)",
+        "value": round(count / t_batch, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{count} independent instances, n log-uniform in [50, 1000] "
+                               f"(sum n = {int(sizes.sum())}), m = n, uniform cities, alpha 1, "
+                               f"beta 2, rho 0.5, {iters} iterations each, gather update, "
+                               "one HIP graph replay",
+                   "count": count, "iterations": iters},
+        "one_instance_per_launch": {"seconds": round(t_single, 4),
+                                    "solves_per_s": round(count / t_single, 2)},
+        "speedup_vs_one_per_launch": round(t_single / t_batch, 2),
+        "ant_steps_per_s": round(ant_steps / t_batch, 1),
+        "tiles": {"sizes": [64, 128, 256, 512, 1024], "chosen": chosen.tolist()},
+    }
+    aco.set_tile(1, 4096, 8)
+    print(json.dumps(rec), flush=True)
+
+
+def bench_served(args, torch, aco):
+    """Poisson arrivals at 200 requests/s, each asking for 50 AS iterations on
+    a fresh instance, n log-uniform in [100, 3000], m = n, uniform or
+    20-cluster layout with equal odds, per-request seed; served by the
+    continuous batcher (admission by slots and pool memory against free HBM),
+    then the same trace served one request at a time on the plain path."""
+    import copy
+
+    from paper_1101_2678_amd import serve
+
+    reqs = serve.make_requests(args.requests, 200.0, n_lo=100, n_hi=3000, iters=50, seed=5)
+    plain_reqs = copy.deepcopy(reqs)
+    free, total = torch.cuda.mem_get_info()
+    pool = min(int(free * 0.5), 64 << 30)
+    footprint = [r.footprint_bytes() for r in reqs]
+    formula = [12 * r.n * r.n + 2 * r.m * r.n for r in reqs]
+    srv = serve.Server(pool_bytes=pool, max_slots=args.slots)
+    log(f"bench served: {len(reqs)} requests, pool {pool / 1e9:.1f} GB, slots {args.slots}")
+    batched = serve.run_open_loop(srv, reqs)
+    srv.close()
+    log(f"bench served: batched {batched}")
+    plain = serve.run_plain(plain_reqs)
+    log(f"bench served: plain {plain}")
+    mismatched = sum(int(a.best_len != b.best_len) for a, b in zip(reqs, plain_reqs))
+    rec = {
+        "metric": "served solves/s and p99 latency (50 AS iterations per request)",
+        "value": round(batched["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": round(batched["makespan_s"] * 1e3 / len(reqs), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, Poisson arrivals at 200/s, n log-uniform "
+                               "in [100, 3000], m = n, uniform or 20-cluster layout (50/50), "
+                               "alpha 1, beta 2, rho 0.5, 50 iterations each, per-request seed",
+                   "requests": len(reqs), "rate_per_s": 200.0, "slots": args.slots,
+                   "pool_bytes": pool},
+        "latency_p50_s": round(batched["latency_p50_s"], 4),
+        "latency_p99_s": round(batched["latency_p99_s"], 4),
+        "batched": batched,
+        "plain_one_request_at_a_time": plain,
+        "results_differing_from_plain": mismatched,
+        "footprint_bytes_total": int(sum(footprint)),
+        "footprint_formula_12n2_2mn_total": int(sum(formula)),
+        "offered_load_note": "offered load exceeds device capacity; latency grows with trace length",
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="n2400")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch256", "served"],
+                    default="n2400")
+    ap.add_argument("--requests", type=int, default=100, help="served workload: trace length")
+    ap.add_argument("--slots", type=int, default=32, help="served workload: server slots")
     ap.add_argument("--update", choices=["gather", "atomic"], default="gather")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time budget of the oracle sample (0 skips it)")
@@ -195,6 +317,12 @@ def main():
         sys.exit(1)
     from paper_1101_2678_amd import aco
 
+    if args.workload == "batch256":
+        bench_batch(args, torch, aco)
+        return
+    if args.workload == "served":
+        bench_served(args, torch, aco)
+        return
     wl = WORKLOADS[args.workload]
     n, m = wl["n"], wl["m"]
     _, d = tsp_inputs.instance(n, wl["layout"], side=wl["side"], seed=wl["seed"])

@@ -244,6 +244,60 @@ aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void
 aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
                           void* hip_stream);
 
+/* ---- serving: continuous batching of independent solves ------------------ */
+
+typedef struct aco_server aco_server; /* opaque; host memory owned by the library */
+
+/* Bytes the server reserves at the head of its pool for the tables of the
+ * running set: max_slots colonies, max_ants ant entries, max_rows row
+ * entries.  0 if an argument is out of range. */
+size_t aco_server_table_bytes(int32_t max_slots, int32_t max_ants, int32_t max_rows);
+
+/* Creates a server over a caller-owned device pool (256-byte aligned,
+ * >= aco_server_table_bytes); the rest of the pool holds request
+ * workspaces.  Ticks run on hip_stream; request initialisation runs on a
+ * stream of the server's own.  At most max_slots requests are held at once,
+ * and the running set never exceeds max_ants ants or max_rows rows in
+ * total. */
+aco_status aco_server_create(aco_server** out, void* d_pool, size_t pool_bytes, int32_t max_slots,
+                             int32_t max_ants, int32_t max_rows, void* hip_stream);
+
+/* Admission: a request for `iters` iterations of instance (p, dist_host) is
+ * admitted if a slot is free, the running set stays within max_ants/max_rows
+ * (else ACO_ERR_STATE) and the pool has a free block of
+ * aco_workspace_bytes(p, 0) bytes (else ACO_ERR_NOMEM); nothing changes on a
+ * refusal.  On success *slot_out receives the slot; the distances are
+ * uploaded and the colony initialised asynchronously, and the request joins
+ * the running set at the first tick after that.  dist_host must stay valid
+ * until aco_server_step has been called once more. */
+aco_status aco_server_submit(aco_server* s, const aco_params* p, const int32_t* dist_host,
+                             uint32_t iters, int64_t request_id, int32_t* slot_out);
+
+/* One tick: every running request advances by one iteration (Section II:
+ * construction, best-so-far, update), all of them in three launches.
+ * *running_out (may be NULL) receives how many ran.  Asynchronous. */
+aco_status aco_server_step(aco_server* s, int32_t* running_out);
+
+/* Waits for the last tick and reports (up to max) requests whose
+ * iterations are all done: their slots and request ids.  Synchronous. */
+aco_status aco_server_collect(aco_server* s, int32_t* slots_out, int64_t* ids_out, int32_t max,
+                              int32_t* count_out);
+
+/* Result of a finished request (best tour n+1 uint16, best length; host),
+ * its final tau (n*n floats, host), and release of its slot and memory. */
+aco_status aco_server_result(aco_server* s, int32_t slot, uint16_t* best_tour_host,
+                             int64_t* best_len_host);
+aco_status aco_server_read_tau(aco_server* s, int32_t slot, float* tau_host);
+aco_status aco_server_release(aco_server* s, int32_t slot);
+
+/* Occupancy: requests running, initialising and finished-but-held, free
+ * pool bytes, the largest free block, ticks so far.  Any pointer may be
+ * NULL. */
+aco_status aco_server_stats(aco_server* s, int32_t* running, int32_t* initialising,
+                            int32_t* finished, size_t* free_bytes, size_t* largest_free_block,
+                            uint64_t* ticks);
+void aco_server_destroy(aco_server* s);
+
 /* Random-row read probe: the access pattern of tour construction without its
  * arithmetic.  `waves` one-wavefront workgroups each read `steps` whole rows
  * of `row_len` floats from a rows x ld float matrix (device), the row of each

@@ -1,0 +1,233 @@
+"""Serving Ant System solves on one GPU with continuous batching.
+
+``Server`` wraps the C server of libaco (``aco_server_*``): requests are
+admitted while a slot and pool memory are free, initialised on a stream of
+their own, and then advanced together, one AS iteration per tick for every
+running request.  ``run_open_loop`` replays an arrival trace against a
+server and records per-request latency; ``run_plain`` serves the same trace
+one request at a time with a context of its own, for comparison.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import aco as _aco
+from .aco import ACO_ERR_NOMEM, ACO_ERR_STATE, ACO_OK, AcoError, Params, _check, _stream_handle
+
+lib = _aco.lib
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the trace
+    dist: np.ndarray        # (n, n) int32
+    m: int
+    iters: int
+    seed: int
+    alpha: int = 1
+    beta: int = 2
+    rho: float = 0.5
+    layout: str = "uniform"
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    best_len: int = -1
+    best_tour: np.ndarray | None = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.dist.shape[0])
+
+    def footprint_bytes(self) -> int:
+        return _aco.workspace_bytes(self.n, self.m, self.alpha, self.beta, self.rho, self.seed,
+                                    atomic=False)
+
+
+class Server:
+    """A device pool, slots, and the running set of a continuous batcher."""
+
+    def __init__(self, pool_bytes: int | None = None, max_slots: int = 32,
+                 max_ants: int = 1 << 18, max_rows: int = 1 << 18, device="cuda",
+                 stream=None, pool_fraction: float = 0.5):
+        import torch
+
+        self.device = torch.device(device)
+        free, _total = torch.cuda.mem_get_info(self.device)
+        if pool_bytes is None:
+            pool_bytes = int(free * pool_fraction)
+        self.pool_bytes = int(pool_bytes) // 256 * 256
+        self.pool = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.max_slots = max_slots
+        self._s = ctypes.c_void_p()
+        _check(lib.aco_server_create(ctypes.byref(self._s), ctypes.c_void_p(self.pool.data_ptr()),
+                                     self.pool_bytes, max_slots, max_ants, max_rows,
+                                     _stream_handle(self.stream)), "aco_server_create")
+        self._held = {}
+
+    def submit(self, req: Request) -> int | None:
+        """Admits `req` if a slot and pool memory are free; None if refused."""
+        p = Params(req.n, req.m, req.alpha, req.beta, req.rho, req.seed)
+        slot = ctypes.c_int32(-1)
+        d = np.ascontiguousarray(req.dist, np.int32)
+        st = lib.aco_server_submit(self._s, ctypes.byref(p), d.ctypes.data_as(ctypes.c_void_p),
+                                   req.iters, req.rid, ctypes.byref(slot))
+        if st in (ACO_ERR_NOMEM, ACO_ERR_STATE):
+            return None
+        _check(st, "aco_server_submit")
+        self._held[slot.value] = d  # keeps the host distances alive
+        return slot.value
+
+    def step(self) -> int:
+        running = ctypes.c_int32()
+        _check(lib.aco_server_step(self._s, ctypes.byref(running)), "aco_server_step")
+        return running.value
+
+    def collect(self):
+        slots = np.zeros(self.max_slots, np.int32)
+        ids = np.zeros(self.max_slots, np.int64)
+        cnt = ctypes.c_int32()
+        _check(lib.aco_server_collect(self._s, slots.ctypes.data_as(ctypes.c_void_p),
+                                      ids.ctypes.data_as(ctypes.c_void_p), self.max_slots,
+                                      ctypes.byref(cnt)), "aco_server_collect")
+        return list(zip(slots[:cnt.value].tolist(), ids[:cnt.value].tolist()))
+
+    def result(self, slot: int, n: int):
+        tour = np.empty(n + 1, np.uint16)
+        length = ctypes.c_int64()
+        _check(lib.aco_server_result(self._s, slot, tour.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.byref(length)), "aco_server_result")
+        return tour, int(length.value)
+
+    def tau(self, slot: int, n: int):
+        out = np.empty((n, n), np.float32)
+        _check(lib.aco_server_read_tau(self._s, slot, out.ctypes.data_as(ctypes.c_void_p)),
+               "aco_server_read_tau")
+        return out
+
+    def release(self, slot: int):
+        _check(lib.aco_server_release(self._s, slot), "aco_server_release")
+        self._held.pop(slot, None)
+
+    def stats(self) -> dict:
+        r, i, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        fb, lb, t = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_uint64()
+        _check(lib.aco_server_stats(self._s, ctypes.byref(r), ctypes.byref(i), ctypes.byref(f),
+                                    ctypes.byref(fb), ctypes.byref(lb), ctypes.byref(t)),
+               "aco_server_stats")
+        return dict(running=r.value, initialising=i.value, finished=f.value,
+                    free_bytes=fb.value, largest_free_block=lb.value, ticks=t.value)
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib.aco_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_requests(count: int, rate_per_s: float, n_lo: int = 100, n_hi: int = 3000,
+                  iters: int = 50, seed: int = 5, side: int = 1_000_000):
+    """Poisson arrivals; n log-uniform in [n_lo, n_hi]; m = n; uniform or
+    20-cluster layout with equal odds; per-request seed = request id + 1."""
+    import tsp_inputs
+
+    arrivals = tsp_inputs.poisson_arrivals(count, rate_per_s, seed)
+    sizes = tsp_inputs.log_uniform_sizes(count, n_lo, n_hi, seed)
+    coin = np.random.default_rng([seed, 0x5EED_0005]).random(count) < 0.5
+    reqs = []
+    for i in range(count):
+        layout = "cluster" if coin[i] else "uniform"
+        _, d = tsp_inputs.instance(int(sizes[i]), layout, side=side, seed=10_000 + i)
+        reqs.append(Request(rid=i, arrival=float(arrivals[i]), dist=d, m=int(sizes[i]),
+                            iters=iters, seed=i + 1, layout=layout))
+    return reqs
+
+
+def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: float = 2e-4):
+    """Replays the arrival trace in real time: arrivals join a FIFO queue, the
+    head is admitted as soon as the server accepts it, ticks run while any
+    request is active, finished requests are read and released."""
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    queue: deque = deque()
+    slot_req = {}
+    by_id = {r.rid: r for r in requests}
+    done = 0
+    peak = 0
+    t0 = time.perf_counter()
+    while done < len(requests):
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            queue.append(pending.popleft())
+        while queue:
+            slot = server.submit(queue[0])
+            if slot is None:
+                break
+            r = queue.popleft()
+            r.admitted = time.perf_counter() - t0
+            slot_req[slot] = r
+        running = server.step()
+        peak = max(peak, running)
+        for slot, rid in server.collect():
+            r = by_id[rid]
+            r.finished = time.perf_counter() - t0
+            r.best_tour, r.best_len = server.result(slot, r.n)
+            if keep_tau:
+                r.extra["tau"] = server.tau(slot, r.n)
+            server.release(slot)
+            slot_req.pop(slot, None)
+            done += 1
+        if running == 0 and not slot_req:
+            if pending:
+                wait = pending[0].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.01))
+        elif running == 0:
+            time.sleep(idle_sleep)  # requests still initialising
+    return summarize(requests, peak)
+
+
+def run_plain(requests, device="cuda"):
+    """The plain path: one request at a time, in arrival order, each with a
+    context of its own (init + `iters` iterations, one instance per launch)."""
+    import torch
+
+    t0 = time.perf_counter()
+    for r in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        r.admitted = time.perf_counter() - t0
+        c = _aco.Colony(r.dist, r.m, r.alpha, r.beta, r.rho, r.seed, atomic=False, device=device)
+        r.best_tour, r.best_len = c.solve(r.iters, "gather")
+        r.finished = time.perf_counter() - t0
+        c.close()
+        del c
+    torch.cuda.synchronize()
+    return summarize(requests, 1)
+
+
+def summarize(requests, peak_running: int) -> dict:
+    lat = np.array([r.finished - r.arrival for r in requests])
+    first = min(r.arrival for r in requests)
+    last = max(r.finished for r in requests)
+    return {
+        "requests": len(requests),
+        "solves_per_s": len(requests) / (last - first),
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_mean_s": float(lat.mean()),
+        "latency_max_s": float(lat.max()),
+        "makespan_s": last - first,
+        "peak_running": peak_running,
+    }
