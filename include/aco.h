@@ -249,18 +249,22 @@ aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float
 typedef struct aco_server aco_server; /* opaque; host memory owned by the library */
 
 /* Bytes the server reserves at the head of its pool for the tables of the
- * running set: max_slots colonies, max_ants ant entries, max_rows row
- * entries.  0 if an argument is out of range. */
-size_t aco_server_table_bytes(int32_t max_slots, int32_t max_ants, int32_t max_rows);
+ * running sets: per size class, max_slots colonies, max_ants ant entries and
+ * max_rows row entries.  0 if an argument is out of range. */
+size_t aco_server_table_bytes(int32_t max_slots, int32_t max_ants, int32_t max_rows,
+                              int32_t num_classes);
 
 /* Creates a server over a caller-owned device pool (256-byte aligned,
  * >= aco_server_table_bytes); the rest of the pool holds request
- * workspaces.  Ticks run on hip_stream; request initialisation runs on a
- * stream of the server's own.  At most max_slots requests are held at once,
- * and the running set never exceeds max_ants ants or max_rows rows in
- * total. */
+ * workspaces.  Requests are sorted into num_classes (1..8) size classes by
+ * n: class c takes n <= class_max_n[c] (increasing; the last class also
+ * takes anything larger).  Each class ticks on a stream of the server's own,
+ * independently of the others; request initialisation runs on another.  At
+ * most max_slots requests are held at once, and the requests of one class
+ * never exceed max_ants ants or max_rows rows in total. */
 aco_status aco_server_create(aco_server** out, void* d_pool, size_t pool_bytes, int32_t max_slots,
-                             int32_t max_ants, int32_t max_rows, void* hip_stream);
+                             int32_t max_ants, int32_t max_rows, int32_t num_classes,
+                             const int32_t* class_max_n);
 
 /* Admission: a request for `iters` iterations of instance (p, dist_host) is
  * admitted if a slot is free, the running set stays within max_ants/max_rows
@@ -273,13 +277,17 @@ aco_status aco_server_create(aco_server** out, void* d_pool, size_t pool_bytes, 
 aco_status aco_server_submit(aco_server* s, const aco_params* p, const int32_t* dist_host,
                              uint32_t iters, int64_t request_id, int32_t* slot_out);
 
-/* One tick: every running request advances by one iteration (Section II:
- * construction, best-so-far, update), all of them in three launches.
- * *running_out (may be NULL) receives how many ran.  Asynchronous. */
+/* Progress without blocking: completes the ticks that have finished (a
+ * request whose iterations are all done becomes finished), lets requests
+ * whose initialisation has finished join their class, and starts the next
+ * tick of every idle class that has running requests.  A tick advances each
+ * running request of the class by one iteration (Section II: construction,
+ * best-so-far, update) in three launches.  *running_out (may be NULL)
+ * receives the number of requests in ticks now in flight. */
 aco_status aco_server_step(aco_server* s, int32_t* running_out);
 
-/* Waits for the last tick and reports (up to max) requests whose
- * iterations are all done: their slots and request ids.  Synchronous. */
+/* Reports (up to max) finished requests not reported before: their slots
+ * and request ids.  Does not block. */
 aco_status aco_server_collect(aco_server* s, int32_t* slots_out, int64_t* ids_out, int32_t max,
                               int32_t* count_out);
 

@@ -69,8 +69,8 @@ def _load():
         "aco_batch_get_iter": (i32, [vp, i32, c.POINTER(u32)]),
         "aco_batch_sync": (i32, [vp]),
         "aco_batch_destroy": (None, [vp]),
-        "aco_server_table_bytes": (sz, [i32, i32, i32]),
-        "aco_server_create": (i32, [c.POINTER(vp), vp, sz, i32, i32, i32, vp]),
+        "aco_server_table_bytes": (sz, [i32, i32, i32, i32]),
+        "aco_server_create": (i32, [c.POINTER(vp), vp, sz, i32, i32, i32, i32, vp]),
         "aco_server_submit": (i32, [vp, c.POINTER(Params), vp, u32, i64, c.POINTER(i32)]),
         "aco_server_step": (i32, [vp, c.POINTER(i32)]),
         "aco_server_collect": (i32, [vp, vp, vp, i32, c.POINTER(i32)]),

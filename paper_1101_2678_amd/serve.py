@@ -2,8 +2,9 @@
 
 ``Server`` wraps the C server of libaco (``aco_server_*``): requests are
 admitted while a slot and pool memory are free, initialised on a stream of
-their own, and then advanced together, one AS iteration per tick for every
-running request.  ``run_open_loop`` replays an arrival trace against a
+their own, and then advanced together by size class, one AS iteration per
+tick for every running request of the class, each class ticking on its own
+stream.  ``run_open_loop`` replays an arrival trace against a
 server and records per-request latency; ``run_plain`` serves the same trace
 one request at a time with a context of its own, for comparison.
 """
@@ -53,8 +54,8 @@ class Server:
     """A device pool, slots, and the running set of a continuous batcher."""
 
     def __init__(self, pool_bytes: int | None = None, max_slots: int = 32,
-                 max_ants: int = 1 << 18, max_rows: int = 1 << 18, device="cuda",
-                 stream=None, pool_fraction: float = 0.5):
+                 max_ants: int = 1 << 18, max_rows: int = 1 << 18,
+                 class_max_n=(384, 1024, 4096), device="cuda", pool_fraction: float = 0.5):
         import torch
 
         self.device = torch.device(device)
@@ -63,12 +64,14 @@ class Server:
             pool_bytes = int(free * pool_fraction)
         self.pool_bytes = int(pool_bytes) // 256 * 256
         self.pool = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        torch.cuda.synchronize(self.device)
         self.max_slots = max_slots
+        self.class_max_n = tuple(int(x) for x in class_max_n)
+        bounds = (ctypes.c_int32 * len(self.class_max_n))(*self.class_max_n)
         self._s = ctypes.c_void_p()
         _check(lib.aco_server_create(ctypes.byref(self._s), ctypes.c_void_p(self.pool.data_ptr()),
                                      self.pool_bytes, max_slots, max_ants, max_rows,
-                                     _stream_handle(self.stream)), "aco_server_create")
+                                     len(self.class_max_n), bounds), "aco_server_create")
         self._held = {}
 
     def submit(self, req: Request) -> int | None:
@@ -154,10 +157,11 @@ def make_requests(count: int, rate_per_s: float, n_lo: int = 100, n_hi: int = 30
     return reqs
 
 
-def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: float = 2e-4):
+def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: float = 1e-4):
     """Replays the arrival trace in real time: arrivals join a FIFO queue, the
-    head is admitted as soon as the server accepts it, ticks run while any
-    request is active, finished requests are read and released."""
+    head is admitted as soon as the server accepts it, the server is polled
+    (each size class ticks on its own), and finished requests are read and
+    released."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     queue: deque = deque()
     slot_req = {}
@@ -172,13 +176,17 @@ def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: 
         while queue:
             slot = server.submit(queue[0])
             if slot is None:
+                if not slot_req:
+                    raise RuntimeError(f"request {queue[0].rid} (n={queue[0].n}) can never be "
+                                       "admitted: pool, slots or class capacity too small")
                 break
             r = queue.popleft()
             r.admitted = time.perf_counter() - t0
             slot_req[slot] = r
         running = server.step()
         peak = max(peak, running)
-        for slot, rid in server.collect():
+        finished = server.collect()
+        for slot, rid in finished:
             r = by_id[rid]
             r.finished = time.perf_counter() - t0
             r.best_tour, r.best_len = server.result(slot, r.n)
@@ -187,13 +195,12 @@ def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: 
             server.release(slot)
             slot_req.pop(slot, None)
             done += 1
-        if running == 0 and not slot_req:
-            if pending:
-                wait = pending[0].arrival - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.01))
-        elif running == 0:
-            time.sleep(idle_sleep)  # requests still initialising
+        if not slot_req and not queue and pending:
+            wait = pending[0].arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+        elif not finished:
+            time.sleep(idle_sleep)  # ticks or initialisations in flight
     return summarize(requests, peak)
 
 

@@ -177,16 +177,22 @@ def test_autotune_validation(aco):
 
 
 def test_server_validation(aco):
-    assert aco.lib.aco_server_table_bytes(0, 10, 10) == 0
-    assert aco.lib.aco_server_table_bytes(10, 0, 10) == 0
-    head = aco.lib.aco_server_table_bytes(4, 100, 100)
+    assert aco.lib.aco_server_table_bytes(0, 10, 10, 1) == 0
+    assert aco.lib.aco_server_table_bytes(10, 0, 10, 1) == 0
+    assert aco.lib.aco_server_table_bytes(10, 10, 10, 9) == 0
+    head = aco.lib.aco_server_table_bytes(4, 100, 100, 1)
     assert head >= 4 * 64 + 400 + 400 and head % 256 == 0
+    assert aco.lib.aco_server_table_bytes(4, 100, 100, 3) == 3 * head
     s = ctypes.c_void_p()
-    assert aco.lib.aco_server_create(ctypes.byref(s), None, 1 << 20, 4, 100, 100,
-                                     None) == aco.ACO_ERR_NOMEM
-    assert aco.lib.aco_server_create(ctypes.byref(s), 0x100000, 16, 4, 100, 100,
-                                     None) == aco.ACO_ERR_NOMEM
-    assert aco.lib.aco_server_create(ctypes.byref(s), 0x100000, 1 << 20, 0, 100, 100,
-                                     None) == aco.ACO_ERR_INVALID
+    b1 = (ctypes.c_int32 * 1)(4096)
+    b2 = (ctypes.c_int32 * 2)(500, 400)
+    assert aco.lib.aco_server_create(ctypes.byref(s), None, 1 << 20, 4, 100, 100, 1,
+                                     b1) == aco.ACO_ERR_NOMEM
+    assert aco.lib.aco_server_create(ctypes.byref(s), 0x100000, 16, 4, 100, 100, 1,
+                                     b1) == aco.ACO_ERR_NOMEM
+    assert aco.lib.aco_server_create(ctypes.byref(s), 0x100000, 1 << 20, 0, 100, 100, 1,
+                                     b1) == aco.ACO_ERR_INVALID
+    assert aco.lib.aco_server_create(ctypes.byref(s), 0x100000, 1 << 20, 4, 100, 100, 2,
+                                     b2) == aco.ACO_ERR_INVALID  # bounds not increasing
     assert aco.lib.aco_server_step(None, None) == aco.ACO_ERR_INVALID
     aco.lib.aco_server_destroy(None)

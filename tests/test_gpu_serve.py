@@ -3,6 +3,8 @@ give exactly the result it gives alone; admission follows slots, table
 limits and pool memory."""
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import pytest
 
@@ -61,7 +63,7 @@ def test_admission_waits_for_memory():
     r2 = Request(rid=2, arrival=0.0, dist=d2, m=280, iters=5, seed=4)
     from paper_1101_2678_amd.aco import lib
 
-    head = lib.aco_server_table_bytes(4, 4096, 4096)
+    head = lib.aco_server_table_bytes(4, 4096, 4096, 3)
     pool = head + workspace_bytes(300, 300, atomic=False) + 4096
     srv = Server(pool_bytes=pool, max_slots=4, max_ants=4096, max_rows=4096)
     s1 = srv.submit(r1)
@@ -72,6 +74,7 @@ def test_admission_waits_for_memory():
         done = srv.collect()
         if done:
             break
+        time.sleep(1e-4)
     assert done == [(s1, 1)]
     r1.best_tour, r1.best_len = srv.result(s1, 300)
     assert srv.submit(r2) is None  # still held until released
@@ -80,6 +83,7 @@ def test_admission_waits_for_memory():
     assert s2 is not None
     while not srv.collect():
         srv.step()
+        time.sleep(1e-4)
     r2.best_tour, r2.best_len = srv.result(s2, 280)
     srv.release(s2)
     for r in (r1, r2):
@@ -96,5 +100,27 @@ def test_admission_respects_table_limits():
     srv = Server(pool_bytes=64 << 20, max_slots=8, max_ants=150, max_rows=1000)
     a = srv.submit(Request(rid=1, arrival=0, dist=d, m=100, iters=2, seed=1))
     b = srv.submit(Request(rid=2, arrival=0, dist=d, m=100, iters=2, seed=2))
-    assert a is not None and b is None  # 200 ants > 150
+    assert a is not None and b is None  # 200 ants > 150 in one size class
+    _, d2 = tsp_inputs.instance(600, "uniform", side=10_000, seed=6)
+    c = srv.submit(Request(rid=3, arrival=0, dist=d2, m=100, iters=2, seed=3))
+    assert c is not None  # another size class has its own capacity
+    srv.close()
+
+
+def test_small_requests_not_paced_by_large():
+    """A small request submitted beside a large one finishes first: each size
+    class ticks on its own."""
+    from paper_1101_2678_amd.serve import Request, Server
+
+    _, big = tsp_inputs.instance(2400, "uniform", side=1_000_000, seed=7)
+    _, small = tsp_inputs.instance(100, "uniform", side=1_000_000, seed=8)
+    srv = Server(pool_bytes=1 << 30, max_slots=4)
+    sb = srv.submit(Request(rid=1, arrival=0, dist=big, m=2400, iters=6, seed=1))
+    ss = srv.submit(Request(rid=2, arrival=0, dist=small, m=100, iters=6, seed=2))
+    order = []
+    while len(order) < 2:
+        srv.step()
+        order += [rid for _, rid in srv.collect()]
+        time.sleep(1e-4)
+    assert order == [2, 1], order
     srv.close()
