@@ -13,7 +13,7 @@
 //           tour neighbours of city i in every ant's tour), accumulates the
 //           deposits in binary64 LDS slots, then evaporates, adds and
 //           refreshes the choice row.  No global atomics.
-//   atomic  (Section III-B, "a thread per city in an ant's tour"): each tour
+//   atomic  (Section III-B, one thread per city of an ant's tour): each tour
 //           edge adds its deposit to both (i, j) and (j, i) of a binary64
 //           matrix with global atomics; an epilogue pass evaporates, adds,
 //           refreshes the choice matrix and clears the deposit matrix.
