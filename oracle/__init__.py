@@ -79,6 +79,11 @@ def lib():
         L.oracle_construct_ant.argtypes = [c.c_int32, _f32p, _i32p, c.c_uint64, c.c_uint32,
                                            c.c_uint32, _u16p]
         L.oracle_construct_ant.restype = c.c_int64
+        L.oracle_nn_lists.argtypes = [c.c_int32, _i32p, c.c_int32, _u16p]
+        L.oracle_nn_lists.restype = None
+        L.oracle_construct_ant_nn.argtypes = [c.c_int32, _f32p, _i32p, _u16p, c.c_int32,
+                                              c.c_uint64, c.c_uint32, c.c_uint32, _u16p]
+        L.oracle_construct_ant_nn.restype = c.c_int64
         L.oracle_construct.argtypes = [c.c_int32, c.c_int32, _f32p, _i32p, c.c_uint64,
                                        c.c_uint32, _u16p, _i64p]
         L.oracle_construct.restype = None
@@ -158,6 +163,45 @@ def construct_ant(choice_m: np.ndarray, dist: np.ndarray, seed: int, it: int, an
                                         np.ascontiguousarray(dist, np.int32), seed, it, ant,
                                         tour)
     return tour, int(length)
+
+
+def nn_lists(dist: np.ndarray, nn: int) -> np.ndarray:
+    n = dist.shape[0]
+    out = np.empty((n, nn), np.uint16)
+    lib().oracle_nn_lists(n, np.ascontiguousarray(dist, np.int32), nn, out)
+    return out
+
+
+def construct_ant_nn(choice_m, dist, nnl, seed: int, it: int, ant: int):
+    n = dist.shape[0]
+    nnl = np.ascontiguousarray(nnl, np.uint16)
+    tour = np.empty(n + 1, np.uint16)
+    length = lib().oracle_construct_ant_nn(n, np.ascontiguousarray(choice_m, np.float32),
+                                           np.ascontiguousarray(dist, np.int32), nnl,
+                                           nnl.shape[1], seed, it, ant, tour)
+    return tour, int(length)
+
+
+def construct_nn(choice_m, dist, nnl, m: int, seed: int, it: int, threads: int = 1):
+    """All m nn-list tours of iteration ``it`` (each ant one serial call)."""
+    n = dist.shape[0]
+    tours = np.empty((m, n + 1), np.uint16)
+    lens = np.empty(m, np.int64)
+
+    def one(k):
+        t, ln = construct_ant_nn(choice_m, dist, nnl, seed, it, k)
+        tours[k] = t
+        lens[k] = ln
+
+    if threads <= 1:
+        for k in range(m):
+            one(k)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(m)))
+    return tours, lens
 
 
 def construct(choice_m: np.ndarray, dist: np.ndarray, m: int, seed: int, it: int,

@@ -224,6 +224,75 @@ int64_t oracle_construct_ant(int32_t n, const float* choice, const int32_t* dist
     return len;
 }
 
+void oracle_nn_lists(int32_t n, const int32_t* dist, int32_t nn, uint16_t* out) {
+    uint8_t* taken = (uint8_t*)malloc((size_t)n);
+    if (!taken) return;
+    for (int32_t i = 0; i < n; ++i) {
+        memset(taken, 0, (size_t)n);
+        taken[i] = 1;
+        for (int32_t r = 0; r < nn; ++r) {
+            int32_t best = -1;
+            for (int32_t j = 0; j < n; ++j) {
+                if (taken[j]) continue;
+                if (best < 0 || dist[(int64_t)i * n + j] < dist[(int64_t)i * n + best]) best = j;
+            }
+            out[(int64_t)i * nn + r] = (uint16_t)best;
+            taken[best] = 1;
+        }
+    }
+    free(taken);
+}
+
+int64_t oracle_construct_ant_nn(int32_t n, const float* choice, const int32_t* dist,
+                                const uint16_t* nnl, int32_t nn, uint64_t seed, uint32_t iter,
+                                uint32_t ant, uint16_t* tour) {
+    uint8_t* feasible = (uint8_t*)malloc((size_t)n);
+    float* cand_w = (float*)malloc(sizeof(float) * (size_t)nn);
+    uint8_t* cand_f = (uint8_t*)malloc((size_t)nn);
+    if (!feasible || !cand_w || !cand_f) {
+        free(feasible);
+        free(cand_w);
+        free(cand_f);
+        return -1;
+    }
+    memset(feasible, 1, (size_t)n);
+    int32_t cur = oracle_start_city(oracle_draw(seed, iter, ant, 0), n);
+    tour[0] = (uint16_t)cur;
+    feasible[cur] = 0;
+    int64_t len = 0;
+    for (int32_t step = 1; step < n; ++step) {
+        float u = oracle_uniform(oracle_draw(seed, iter, ant, (uint32_t)step));
+        const uint16_t* list = nnl + (int64_t)cur * nn;
+        int any = 0;
+        for (int32_t r = 0; r < nn; ++r) {
+            cand_w[r] = choice[(int64_t)cur * n + list[r]];
+            cand_f[r] = feasible[list[r]];
+            any |= cand_f[r];
+        }
+        int32_t next;
+        if (any) {
+            next = list[oracle_r64_select(nn, cand_w, cand_f, u)];
+        } else {
+            next = -1;
+            for (int32_t j = 0; j < n; ++j) {
+                if (!feasible[j]) continue;
+                if (next < 0 || choice[(int64_t)cur * n + j] > choice[(int64_t)cur * n + next])
+                    next = j;
+            }
+        }
+        tour[step] = (uint16_t)next;
+        feasible[next] = 0;
+        len += dist[(int64_t)cur * n + next];
+        cur = next;
+    }
+    tour[n] = tour[0];
+    len += dist[(int64_t)cur * n + tour[0]];
+    free(feasible);
+    free(cand_w);
+    free(cand_f);
+    return len;
+}
+
 void oracle_construct(int32_t n, int32_t m, const float* choice, const int32_t* dist,
                       uint64_t seed, uint32_t iter, uint16_t* tours, int64_t* lens) {
     for (int32_t k = 0; k < m; ++k)

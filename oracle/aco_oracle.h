@@ -106,6 +106,22 @@ int64_t oracle_construct_ant(int32_t n, const float* choice, const int32_t* dist
 void oracle_construct(int32_t n, int32_t m, const float* choice, const int32_t* dist,
                       uint64_t seed, uint32_t iter, uint16_t* tours, int64_t* lens);
 
+/* Nearest-neighbour lists (Section II, the nn-list variant of construction):
+ * row i holds the nn cities j != i with the smallest d_ij, ordered by
+ * (d_ij, j).  out: n*nn uint16.  1 <= nn <= n-1. */
+void oracle_nn_lists(int32_t n, const int32_t* dist, int32_t nn, uint16_t* out);
+
+/* One ant's tour with nn-list construction: at city i the candidates are the
+ * unvisited entries of row i's list, in list order, weighted by
+ * choice[i][.]; if any candidate is unvisited the next city is drawn by the
+ * R64 roulette over the candidate vector (oracle_r64_select on the nn list
+ * entries, same Philox draw as full construction); otherwise it is the
+ * unvisited city with the largest choice value (lowest index among equal
+ * values).  Returns C^k. */
+int64_t oracle_construct_ant_nn(int32_t n, const float* choice, const int32_t* dist,
+                                const uint16_t* nnl, int32_t nn, uint64_t seed, uint32_t iter,
+                                uint32_t ant, uint16_t* tour);
+
 /* dep_k = fl32(1 / C^k), Eq. (4) with Q = 1. */
 float oracle_deposit_amount(int64_t len);
 

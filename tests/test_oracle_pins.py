@@ -411,6 +411,150 @@ def test_alpha_beta_zero_uniform_second_city(oracle_lib):
         assert stats.chisquare(row).pvalue > 1e-4
 
 
+# ----------------------------------------------------------------- nn-list construction
+def _grid_instance(rows, cols, step=10):
+    """Cities on an integer grid: many equal distances, so every tie rule
+    is exercised."""
+    xy = np.array([[step * c, step * r] for r in range(rows) for c in range(cols)], np.int64)
+    return tsp_inputs.euc2d(xy)
+
+
+@pytest.mark.parametrize("layout", ["uniform", "cluster", "grid"])
+def test_nn_lists_match_lexsort(oracle_lib, layout):
+    """Row i lists the nn nearest other cities by (d_ij, j), like a stable
+    sort of the row by distance with city i removed."""
+    if layout == "grid":
+        d = _grid_instance(7, 9)
+    else:
+        _, d = tsp_inputs.instance(200, layout, side=3000, seed=8)
+    n = d.shape[0]
+    for nn in (1, 5, 30, n - 1):
+        got = oracle_lib.nn_lists(d, nn)
+        for i in range(n):
+            others = np.delete(np.arange(n), i)
+            order = others[np.lexsort((others, d[i, others]))]
+            assert got[i].tolist() == order[:nn].tolist(), (layout, nn, i)
+
+
+@pytest.mark.parametrize("n", [5, 64, 65, 130])
+def test_nn_full_list_reduces_to_full_construction(oracle_lib, n):
+    """With equal distances every list is 0..n-1 without i; with nn = n-1
+    and integer weights (exact sums) the nn-list roulette then picks the
+    same city as the roulette over the whole row, so the tours coincide
+    with full construction.  The weights are not symmetric, so a
+    transposed lookup would show."""
+    d = np.full((n, n), 7, np.int32)
+    np.fill_diagonal(d, 0)
+    rng = np.random.default_rng(n)
+    choice = rng.integers(0, 9, size=(n, n)).astype(np.float32)
+    np.fill_diagonal(choice, 0)
+    nnl = oracle_lib.nn_lists(d, n - 1)
+    for i in range(n):
+        assert nnl[i].tolist() == [j for j in range(n) if j != i]
+    for k in range(40):
+        t_nn, l_nn = oracle_lib.construct_ant_nn(choice, d, nnl, 3, 2, k)
+        t_full, l_full = oracle_lib.construct_ant(choice, d, 3, 2, k)
+        assert t_nn.tolist() == t_full.tolist() and l_nn == l_full
+
+
+def _greedy_tour(d, start):
+    """Textbook nearest-neighbour tour: always the closest unvisited city,
+    the lowest index among equally close ones."""
+    n = d.shape[0]
+    seen = [False] * n
+    tour = [start]
+    seen[start] = True
+    for _ in range(n - 1):
+        cur = tour[-1]
+        nxt = min((j for j in range(n) if not seen[j]), key=lambda j: (d[cur, j], j))
+        tour.append(nxt)
+        seen[nxt] = True
+    return tour + [start]
+
+
+@pytest.mark.parametrize("case", ["uniform", "grid"])
+def test_nn_one_with_decreasing_choice_is_greedy_tour(oracle_lib, case):
+    """nn = 1 and choice strictly decreasing in d: the listed neighbour is
+    the nearest city, and the fallback (largest choice among the unvisited)
+    is the nearest unvisited city, so every tour is the nearest-neighbour
+    tour from its start city."""
+    if case == "grid":
+        d = _grid_instance(5, 6)
+    else:
+        _, d = tsp_inputs.instance(60, "uniform", side=100_000, seed=5)
+    n = d.shape[0]
+    with np.errstate(divide="ignore"):
+        choice = (1.0 / (d.astype(np.float64) ** 2)).astype(np.float32)
+    np.fill_diagonal(choice, 0)
+    nnl = oracle_lib.nn_lists(d, 1)
+    for k in range(25):
+        t, ln = oracle_lib.construct_ant_nn(choice, d, nnl, 11, 0, k)
+        start = oracle_lib.start_city(oracle_lib.draw(11, 0, k, 0), n)
+        want = _greedy_tour(d, start)
+        assert t.tolist() == want
+        assert ln == tour_length(d, want)
+
+
+def test_nn_fallback_takes_largest_choice_lowest_index(oracle_lib):
+    """Once the listed neighbours are visited the ant goes to the unvisited
+    city with the largest choice value; equal values go to the lowest
+    index.  Choice values here are chosen so that this city is never the
+    nearest one."""
+    n = 12
+    _, d = tsp_inputs.instance(n, "uniform", side=1000, seed=3)
+    nnl = oracle_lib.nn_lists(d, 1)
+    # choice[i][j] = j mod 4 (ties in groups): the argmax over unvisited j is
+    # the lowest unvisited j with the largest residue
+    choice = np.tile((np.arange(n) % 4).astype(np.float32), (n, 1))
+    np.fill_diagonal(choice, 0)
+    for k in range(30):
+        t, _ = oracle_lib.construct_ant_nn(choice, d, nnl, 4, 1, k)
+        seen = {int(t[0])}
+        for s in range(1, n):
+            cur = int(t[s - 1])
+            nb = int(nnl[cur, 0])
+            unv = [j for j in range(n) if j not in seen]
+            if nb not in seen:
+                want = nb
+            else:
+                best = max(choice[cur, j] for j in unv)
+                want = min(j for j in unv if choice[cur, j] == best)
+            assert int(t[s]) == want, (k, s)
+            seen.add(want)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_nn_second_city_follows_eq1_on_the_list(oracle_lib, seed):
+    """At step 1 only the start is visited and it is on no list of its
+    own, so the second city is drawn from the start's list with
+    probabilities choice / (sum over the list): Eq. (1) restricted to the
+    candidate list."""
+    n, nn, ants = 7, 3, 21000
+    _, d = tsp_inputs.instance(n, "uniform", side=1000, seed=6)
+    st = oracle_lib.init(d, 7, 1, 2, 0.5, 1)
+    nnl = oracle_lib.nn_lists(d, nn)
+    tours, _ = oracle_lib.construct_nn(st.choice, d, nnl, ants, seed, 0, threads=4)
+    for s in range(n):
+        sec = tours[tours[:, 0] == s, 1]
+        assert set(sec.tolist()) <= set(nnl[s].tolist())
+        w = st.choice[s, nnl[s]].astype(np.float64)
+        obs = np.array([(sec == c).sum() for c in nnl[s]])
+        assert stats.chisquare(obs, w / w.sum() * obs.sum()).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("n,nn", [(3, 1), (3, 2), (40, 5), (130, 30), (257, 64)])
+def test_nn_tours_are_permutations(oracle_lib, n, nn):
+    _, d = tsp_inputs.instance(n, "cluster", side=20_000, seed=n)
+    st = oracle_lib.init(d, 8, 1, 2, 0.5, 2)
+    nnl = oracle_lib.nn_lists(d, nn)
+    tours, lens = oracle_lib.construct_nn(st.choice, d, nnl, 8, 2, 0)
+    for k in range(8):
+        t = tours[k]
+        assert sorted(t[:-1].tolist()) == list(range(n)) and t[n] == t[0]
+        assert t[0] == oracle_lib.start_city(oracle_lib.draw(2, 0, k, 0), n)
+        assert lens[k] == tour_length(d, t)
+
+
 # ----------------------------------------------------------------- update (C9-C11)
 def test_evaporation_closed_form(oracle_lib):
     """Cells no tour touches follow tau0 * (1 - rho)^k (Eq. 2)."""
