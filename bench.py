@@ -172,6 +172,128 @@ def probe_bandwidth(torch, aco, n: int, m: int):
     return {k: (round(v, 1) if isinstance(v, float) else v) for k, v in out.items()}
 
 
+SYNC_LAUNCHES = False
+
+
+def launched(torch):
+    """After a launch: wait for it when --sync-launches is given.  Profiled
+    runs use it: under rocprofv3 on these GPUs, launches queued back to back
+    on one stream did not reliably see each other's results (the host
+    synchronising in between restores them), while per-kernel durations are
+    the same either way."""
+    if SYNC_LAUNCHES:
+        torch.cuda.synchronize()
+
+
+def nn_fallback_steps(tours: np.ndarray, nnl: np.ndarray, chunk: int = 128) -> int:
+    """Steps at which every candidate of the current city was already
+    visited (the ant then scans the whole choice row)."""
+    m, n1 = tours.shape
+    n = n1 - 1
+    steps = np.arange(1, n, dtype=np.int32)[None, :, None]
+    total = 0
+    for k0 in range(0, m, chunk):
+        t = tours[k0:k0 + chunk].astype(np.int64)
+        c = t.shape[0]
+        pos = np.empty((c, n), np.int32)                    # step at which a city is visited
+        np.put_along_axis(pos, t[:, :-1], np.arange(n, dtype=np.int32)[None, :], axis=1)
+        cand = nnl[t[:, :n - 1]].reshape(c, -1).astype(np.int64)  # lists of tour[s-1]
+        cpos = np.take_along_axis(pos, cand, axis=1).reshape(c, n - 1, -1)
+        total += int((cpos < steps).all(axis=2).sum())
+    return total
+
+
+def nn_lists_problem(d: np.ndarray, nnl: np.ndarray):
+    """None if every row lists other cities in non-decreasing distance, else
+    what is wrong (a property check, independent of how lists are built)."""
+    n = d.shape[0]
+    if nnl.max() >= n:
+        return f"a list entry is >= n ({int(nnl.max())})"
+    if (nnl == np.arange(n)[:, None]).any():
+        return "a row lists its own city"
+    dd = np.take_along_axis(d, nnl.astype(np.int64), axis=1)
+    if (np.diff(dd, axis=1) < 0).any():
+        return "a list is not ordered by distance"
+    return None
+
+
+def bench_nn(torch, aco, d, m: int, nn: int, steps: int, warmup: int, update: str, cpu_s: float):
+    """Candidate-list construction (nn nearest cities) on the same instance:
+    `steps` iterations timed like the main loop, HIP events around each
+    construction (candidate-table refresh included)."""
+    n = d.shape[0]
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=False)
+    col.attach_nn(nn)
+    nnl = col.nn_lists()
+    problem = nn_lists_problem(d, nnl)
+    stream = torch.cuda.current_stream()
+    it = 0
+    for _ in range(warmup):
+        col.construct_nn(it)
+        launched(torch)
+        col.update(update)
+        launched(torch)
+        it += 1
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[3 * s].record(stream)
+        col.construct_nn(it)
+        launched(torch)
+        ev[3 * s + 1].record(stream)
+        col.update(update)
+        launched(torch)
+        ev[3 * s + 2].record(stream)
+        it += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_con = float(np.mean([ev[3 * s].elapsed_time(ev[3 * s + 1]) for s in range(steps)]))
+    tours, _ = col.tours()
+    best = col.best()[1]
+    col.close()
+    if problem is None and not (tours < n).all():
+        problem = "a tour holds a city index >= n"
+    fb = nn_fallback_steps(tours, nnl) if problem is None else 0
+    ant_steps = m * (n - 1)
+    frac = fb / ant_steps
+    # bytes one construction must move: a packed candidate row (8 B per list
+    # entry, padded to 32 entries) per step, a 4n-byte choice row per fallback
+    # step, plus the epilogue (d lookups, tours, succ/pred) as in full construction
+    kp = (nn + 31) // 32 * 32
+    alg = ant_steps * 8 * kp + fb * 4 * n + m * (n * 4 + 2 * (n + 1) + 4 * n)
+    out = {
+        "nn": nn,
+        "ms_per_step": round(wall * 1e3 / steps, 4),
+        "value": round(ant_steps / wall * steps, 1),
+        "unit": "ant-steps/s",
+        "construct_ms": round(t_con, 4),
+        "construct_ant_steps_per_s": round(ant_steps / (t_con * 1e-3), 1),
+        "fallback_fraction_last_iter": round(frac, 5),
+        "construct_algorithmic_bytes": int(alg),
+        "construct_GBps": round(alg / (t_con * 1e-3) / 1e9, 1),
+        "bound": "latency (one dependent candidate-row load per step)",
+        "best_len_after_run": int(best),
+    }
+    if problem is not None:
+        out["error"] = problem
+    if cpu_s > 0:
+        import oracle
+
+        st = oracle.init(d, m, ALPHA, BETA, RHO, 1)
+        lists = oracle.nn_lists(d, nn)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < cpu_s:
+            oracle.construct_ant_nn(st.choice, d, lists, 1, 0, k)
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(k * (n - 1) / el, 1), "unit": "ant-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{k} ants of iteration 0 (nn={nn}), one by one"}
+    return out
+
+
 def bench_batch(args, torch, aco):
     """256 independent instances, n = round(exp(U(ln 50, ln 1000))), m = n,
     uniform cities, alpha 1, beta 2, rho 0.5, 25 iterations each, tiles from
@@ -304,8 +426,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time budget of the oracle sample (0 skips it)")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--sync-launches", action="store_true",
+                    help="synchronise with the host after every launch (for profiled runs; "
+                         "ms_per_step then includes the round trips)")
+    ap.add_argument("--nn", type=int, default=30,
+                    help="also time candidate-list construction with lists of this length "
+                         "(0 skips it)")
     args = ap.parse_args()
 
+    global SYNC_LAUNCHES
+    SYNC_LAUNCHES = args.sync_launches
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(DESIGN.md describes how the path would shard)"}))
@@ -333,7 +463,9 @@ def main():
     it = 0
     for _ in range(args.warmup):
         col.construct(it)
+        launched(torch)
         col.update(args.update)
+        launched(torch)
         it += 1
     torch.cuda.synchronize()
 
@@ -344,8 +476,10 @@ def main():
     for s in range(K):
         ev[3 * s].record(stream)
         col.construct(it)
+        launched(torch)
         ev[3 * s + 1].record(stream)
         col.update(args.update)
+        launched(torch)
         ev[3 * s + 2].record(stream)
         it += 1
     torch.cuda.synchronize()
@@ -359,9 +493,11 @@ def main():
     t_other = []
     for _ in range(max(3, min(K, 10))):
         col.construct(it)
+        launched(torch)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         col.update(other)
+        launched(torch)
         e1.record(stream)
         torch.cuda.synchronize()
         t_other.append(e0.elapsed_time(e1))
@@ -371,6 +507,11 @@ def main():
     col.close()
 
     probe = None if args.no_probe else probe_bandwidth(torch, aco, n, m)
+    nn_rec = None
+    if args.nn > 0:
+        log(f"bench: candidate-list construction, nn={args.nn}")
+        nn_rec = bench_nn(torch, aco, d, m, args.nn, K, args.warmup, args.update,
+                          min(3.0, args.cpu_seconds))
 
     ant_steps = m * (n - 1)
     ms_step = wall * 1e3 / K
@@ -425,6 +566,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "probe": probe,
+        "nn_list": nn_rec,
     }
     print(json.dumps(rec), flush=True)
 

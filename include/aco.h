@@ -126,6 +126,44 @@ aco_status aco_update(aco_ctx* c, aco_update_kind kind);
 aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind,
                      uint16_t* best_tour_host, int64_t* best_len_host);
 
+/* ---- nearest-neighbour candidate lists --------------------------------- */
+
+/* Construction over candidate lists (Section II: the ant chooses among the
+ * nn nearest cities of its current city, and takes the best city by the
+ * Eq. (1) value once all of them are visited; nn = 30 in the evaluation of
+ * Section IV).  Rule, bit-exact against the oracle: row i's list holds the
+ * nn cities j != i with the smallest d_ij, ordered by (d_ij, j); at city i,
+ * if some list entry is unvisited, the R64 roulette runs over the list in
+ * list order (weights choice[i][j] of the unvisited entries, +0 for the
+ * others; one 64-entry block) with the same draw u as full construction;
+ * otherwise the next city is the unvisited city with the largest
+ * choice[i][j], lowest j among equal values.  Tours, lengths, deposits and
+ * the update are those of aco_construct / aco_update. */
+
+/* Device bytes of the candidate tables for n cities and lists of nn
+ * (1 <= nn <= min(64, n - 1)); 0 if the arguments are invalid. */
+size_t aco_nn_workspace_bytes(int32_t n, int32_t nn);
+
+/* Builds the lists of length nn from the context's distances on the device
+ * and keeps them for aco_construct_nn.  d_nn_workspace: device buffer of
+ * bytes >= aco_nn_workspace_bytes(n, nn), 256-byte aligned, owned by the
+ * caller and kept alive as long as the context uses it (a later attach
+ * replaces it).  Asynchronous.  Errors: ACO_ERR_INVALID (nn), ACO_ERR_NOMEM
+ * (workspace). */
+aco_status aco_nn_attach(aco_ctx* c, int32_t nn, void* d_nn_workspace, size_t bytes);
+
+/* aco_construct with the candidate-list rule: rebuilds the packed candidate
+ * table from the current choice matrix, then builds the m tours of
+ * iteration `iter`.  Asynchronous.  ACO_ERR_STATE without aco_nn_attach. */
+aco_status aco_construct_nn(aco_ctx* c, uint32_t iter);
+
+/* aco_solve with aco_construct_nn in place of aco_construct.  Synchronous. */
+aco_status aco_solve_nn(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                        uint16_t* best_tour_host, int64_t* best_len_host);
+
+/* Copies the lists (n*nn uint16, row-major, host) out.  Synchronous. */
+aco_status aco_read_nn_lists(aco_ctx* c, uint16_t* lists_host);
+
 /* Copies of the device state into host memory.  Synchronous.
  *   tours: m*(n+1) uint16 of the last construction; lens: m int64 (either may
  *   be NULL); tau, choice: n*n float row-major; best_tour: n+1 uint16. */

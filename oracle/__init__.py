@@ -285,9 +285,14 @@ def init(dist: np.ndarray, m: int, alpha: int, beta: int, rho: float, seed: int)
     return OracleState(n, m, alpha, beta, rho, seed, tau, ch, float(t0.value))
 
 
-def iterate(st: OracleState, dist: np.ndarray, threads: int = 1, keep: bool = False):
-    """One AS iteration: construct (Section II), best-so-far, update (Eqs. 2-4)."""
-    tours, lens = construct(st.choice, dist, st.m, st.seed, st.it, threads)
+def iterate(st: OracleState, dist: np.ndarray, threads: int = 1, keep: bool = False,
+            nnl: np.ndarray | None = None):
+    """One AS iteration: construct (Section II; over the candidate lists
+    ``nnl`` if given), best-so-far, update (Eqs. 2-4)."""
+    if nnl is None:
+        tours, lens = construct(st.choice, dist, st.m, st.seed, st.it, threads)
+    else:
+        tours, lens = construct_nn(st.choice, dist, nnl, st.m, st.seed, st.it, threads)
     best = ctypes.c_int64(st.best_len)
     who = lib().oracle_best_of(st.m, lens, ctypes.byref(best))
     if who >= 0:
@@ -303,8 +308,11 @@ def iterate(st: OracleState, dist: np.ndarray, threads: int = 1, keep: bool = Fa
 
 
 def solve(dist: np.ndarray, m: int, alpha: int, beta: int, rho: float, seed: int,
-          iters: int, threads: int = 1, keep: bool = False) -> OracleState:
+          iters: int, threads: int = 1, keep: bool = False, nn: int | None = None) -> OracleState:
+    """``iters`` iterations from the initial state; nn: candidate-list
+    construction with lists of that length."""
     st = init(dist, m, alpha, beta, rho, seed)
+    nnl = None if nn is None else nn_lists(dist, nn)
     for _ in range(iters):
-        iterate(st, dist, threads, keep)
+        iterate(st, dist, threads, keep, nnl)
     return st

@@ -46,6 +46,11 @@ def _load():
         "aco_update": (i32, [vp, i32]),
         "aco_solve": (i32, [vp, u32, i32, vp, vp]),
         "aco_read_tours": (i32, [vp, vp, vp]),
+        "aco_nn_workspace_bytes": (sz, [i32, i32]),
+        "aco_nn_attach": (i32, [vp, i32, vp, sz]),
+        "aco_construct_nn": (i32, [vp, u32]),
+        "aco_solve_nn": (i32, [vp, u32, i32, vp, vp]),
+        "aco_read_nn_lists": (i32, [vp, vp]),
         "aco_read_tau": (i32, [vp, vp]),
         "aco_read_choice": (i32, [vp, vp]),
         "aco_read_best": (i32, [vp, vp, vp]),
@@ -148,15 +153,40 @@ class Colony:
     def construct(self, it: int):
         _check(lib.aco_construct(self._ctx, it), "aco_construct")
 
+    def attach_nn(self, nn: int = 30):
+        """Builds candidate lists of length nn on the device (see
+        aco_nn_attach); the tables live in a workspace of their own."""
+        import torch
+
+        nbytes = int(lib.aco_nn_workspace_bytes(self.n, nn))
+        if nbytes == 0:
+            _check(ACO_ERR_INVALID, "aco_nn_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib.aco_nn_attach(self._ctx, nn, ctypes.c_void_p(ws.data_ptr()), nbytes),
+               "aco_nn_attach")
+        self.nn_workspace, self.nn = ws, int(nn)
+
+    def construct_nn(self, it: int):
+        _check(lib.aco_construct_nn(self._ctx, it), "aco_construct_nn")
+
+    def nn_lists(self):
+        out = np.empty((self.n, self.nn), np.uint16)
+        _check(lib.aco_read_nn_lists(self._ctx, out.ctypes.data_as(ctypes.c_void_p)),
+               "aco_read_nn_lists")
+        return out
+
     def update(self, kind="gather"):
         _check(lib.aco_update(self._ctx, _KIND[kind]), "aco_update")
 
     # ---- synchronous calls
-    def solve(self, iters: int, kind="gather"):
+    def solve(self, iters: int, kind="gather", rule: str = "r64"):
+        """rule "r64": full-row construction; "nn": candidate lists (needs
+        attach_nn)."""
+        fn = {"r64": lib.aco_solve, "nn": lib.aco_solve_nn}[rule]
         tour = np.empty(self.n + 1, np.uint16)
         length = ctypes.c_int64()
-        _check(lib.aco_solve(self._ctx, iters, _KIND[kind], tour.ctypes.data_as(ctypes.c_void_p),
-                             ctypes.byref(length)), "aco_solve")
+        _check(fn(self._ctx, iters, _KIND[kind], tour.ctypes.data_as(ctypes.c_void_p),
+                  ctypes.byref(length)), "aco_solve" if rule == "r64" else "aco_solve_nn")
         return tour, int(length.value)
 
     def tours(self):

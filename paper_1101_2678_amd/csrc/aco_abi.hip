@@ -9,13 +9,16 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "aco.h"
 #include "aco_host.hpp"
 #include "aco_state.hpp"
+#include "nn.hpp"
 
 struct aco_ctx {
     aco::Colony col;
+    aco::NnTables nn;       // candidate lists; nn.nn == 0 until aco_nn_attach
     hipStream_t stream;
     size_t ws_bytes;
     uint32_t next_iter;     // first iteration aco_solve runs
@@ -293,18 +296,77 @@ aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
     return ACO_OK;
 }
 
-aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind, uint16_t* best_tour_host,
-                     int64_t* best_len_host) {
+static aco_status solve_with(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                             aco_status (*construct)(aco_ctx*, uint32_t),
+                             uint16_t* best_tour_host, int64_t* best_len_host) {
     if (aco_status s = usable(c)) return s;
     if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
         return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
     if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
         return fail(ACO_ERR_INVALID, "unknown update kind");
     for (uint32_t i = 0; i < iters; ++i) {
-        if (aco_status s = aco_construct(c, c->next_iter)) return s;
+        if (aco_status s = construct(c, c->next_iter)) return s;
         if (aco_status s = aco_update(c, kind)) return s;
     }
     return aco_read_best(c, best_tour_host, best_len_host);
+}
+
+aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind, uint16_t* best_tour_host,
+                     int64_t* best_len_host) {
+    return solve_with(c, iters, kind, aco_construct, best_tour_host, best_len_host);
+}
+
+size_t aco_nn_workspace_bytes(int32_t n, int32_t nn) {
+    if (n < 3 || n > aco::kMaxCities || nn < 1 || nn > aco::kMaxNn || nn > n - 1) return 0;
+    return aco::nn_table_bytes(n, nn);
+}
+
+aco_status aco_nn_attach(aco_ctx* c, int32_t nn, void* d_nn_workspace, size_t bytes) {
+    if (aco_status s = usable(c)) return s;
+    if (nn < 1 || nn > aco::kMaxNn || nn > c->col.n - 1)
+        return fail(ACO_ERR_INVALID, "nn must be in [1, min(64, n - 1)]");
+    if (!d_nn_workspace || ((uintptr_t)d_nn_workspace % aco::host::kAlign) != 0)
+        return fail(ACO_ERR_NOMEM, "nn workspace must be a 256-byte aligned device pointer");
+    if (bytes < aco::nn_table_bytes(c->col.n, nn))
+        return fail(ACO_ERR_NOMEM, "nn workspace smaller than aco_nn_workspace_bytes(n, nn)");
+    const aco::NnTables t = aco::nn_carve(static_cast<char*>(d_nn_workspace), c->col.n, nn);
+    const hipError_t e = aco::launch_nn_lists(c->col, t, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "aco_nn_attach");
+    c->nn = t;
+    return ACO_OK;
+}
+
+aco_status aco_construct_nn(aco_ctx* c, uint32_t iter) {
+    if (aco_status s = usable(c)) return s;
+    if (c->nn.nn == 0) return fail(ACO_ERR_STATE, "aco_construct_nn needs aco_nn_attach first");
+    const hipError_t e = aco::launch_construct_nn(c->col, c->nn, iter, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "aco_construct_nn");
+    c->pending = true;
+    c->pending_iter = iter;
+    return ACO_OK;
+}
+
+aco_status aco_solve_nn(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                        uint16_t* best_tour_host, int64_t* best_len_host) {
+    if (aco_status s = usable(c)) return s;
+    if (c->nn.nn == 0) return fail(ACO_ERR_STATE, "aco_solve_nn needs aco_nn_attach first");
+    return solve_with(c, iters, kind, aco_construct_nn, best_tour_host, best_len_host);
+}
+
+aco_status aco_read_nn_lists(aco_ctx* c, uint16_t* lists_host) {
+    if (aco_status s = usable(c)) return s;
+    if (c->nn.nn == 0) return fail(ACO_ERR_STATE, "no candidate lists attached");
+    if (!lists_host) return fail(ACO_ERR_INVALID, "host pointer is NULL");
+    if (aco_status s = sync_ctx(c, "aco_read_nn_lists")) return s;
+    // one contiguous copy of the padded table, repacked on the host
+    std::vector<uint16_t> padded((size_t)c->col.n * c->nn.kp);
+    const hipError_t e = hipMemcpy(padded.data(), c->nn.nnl, padded.size() * sizeof(uint16_t),
+                                   hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_fail(c, e, "aco_read_nn_lists");
+    for (int i = 0; i < c->col.n; ++i)
+        std::memcpy(lists_host + (size_t)i * c->nn.nn, padded.data() + (size_t)i * c->nn.kp,
+                    (size_t)c->nn.nn * sizeof(uint16_t));
+    return ACO_OK;
 }
 
 aco_status aco_read_best(aco_ctx* c, uint16_t* best_tour_host, int64_t* best_len_host) {
@@ -406,9 +468,9 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
     const int pass = 64 * col.tile;
     std::snprintf(buf, len,
                   "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
-                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 atomic=%d",
+                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 atomic=%d nn=%d",
                   col.tile, (col.n + pass - 1) / pass, (col.n + 63) / 64, col.ld,
-                  aco::construct_occupancy(col), cus, lds_cu, c->has_atomic ? 1 : 0);
+                  aco::construct_occupancy(col), cus, lds_cu, c->has_atomic ? 1 : 0, c->nn.nn);
     return ACO_OK;
 }
 

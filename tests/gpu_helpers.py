@@ -37,20 +37,35 @@ def assert_same_f32(got, want, what: str):
 
 
 def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic"),
-                check_choice=True):
-    """Full parity: every iteration's tours, lengths, tau (and choice) bit-exact."""
+                check_choice=True, nn=None):
+    """Full parity: every iteration's tours, lengths, tau (and choice)
+    bit-exact.  nn: construct over candidate lists of that length (the lists
+    themselves are compared first)."""
     from paper_1101_2678_amd.aco import Colony
 
     n = dist.shape[0]
-    log(f"  parity n={n} m={m} alpha={alpha} beta={beta} rho={rho} seed={seed} iters={iters}")
+    log(f"  parity n={n} m={m} alpha={alpha} beta={beta} rho={rho} seed={seed} iters={iters} "
+        f"nn={nn}")
     ref = oracle.init(dist, m, alpha, beta, rho, seed)
     cols = {k: Colony(dist, m, alpha, beta, rho, seed, atomic=(k == "atomic")) for k in kinds}
+    nnl = None
+    if nn is not None:
+        nnl = oracle.nn_lists(dist, nn)
+        for k, col in cols.items():
+            col.attach_nn(nn)
+            got = col.nn_lists()
+            bad = np.nonzero((got != nnl).any(axis=1))[0]
+            assert bad.size == 0, f"{k}: candidate lists of rows {bad[:5].tolist()} differ"
     for k, col in cols.items():
         assert_same_f32(col.tau(), ref.tau, f"{k} tau0")
         if check_choice:
             assert_same_f32(col.choice(), ref.choice, f"{k} initial choice")
     for it in range(iters):
-        tours, lens = oracle.construct(ref.choice, dist, m, seed, it, ORACLE_THREADS)
+        if nnl is None:
+            tours, lens = oracle.construct(ref.choice, dist, m, seed, it, ORACLE_THREADS)
+        else:
+            tours, lens = oracle.construct_nn(ref.choice, dist, nnl, m, seed, it,
+                                              ORACLE_THREADS)
         import ctypes
 
         best = ctypes.c_int64(ref.best_len)
@@ -60,7 +75,10 @@ def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic
         ref.tau, ref.choice = oracle.update(ref.tau, tours, lens, dist, rho, alpha, beta)
         ref.it += 1
         for k, col in cols.items():
-            col.construct(it)
+            if nnl is None:
+                col.construct(it)
+            else:
+                col.construct_nn(it)
             gt, gl = col.tours()
             bad = np.nonzero((gt != tours).any(axis=1))[0]
             assert bad.size == 0, f"{k} it={it}: tours of ants {bad[:5].tolist()} differ"

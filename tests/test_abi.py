@@ -196,3 +196,21 @@ def test_server_validation(aco):
                                      b2) == aco.ACO_ERR_INVALID  # bounds not increasing
     assert aco.lib.aco_server_step(None, None) == aco.ACO_ERR_INVALID
     aco.lib.aco_server_destroy(None)
+
+
+def test_nn_workspace_and_validation(aco):
+    """Candidate-list tables: two 256-byte aligned arrays of n x kp entries
+    (kp = nn rounded up to 32), uint16 lists and uint64 packed candidates."""
+    f = aco.lib.aco_nn_workspace_bytes
+    r256 = lambda v: (v + 255) // 256 * 256
+    for n, nn in [(3, 1), (3, 2), (100, 30), (2400, 30), (4096, 64), (65, 33)]:
+        kp = (nn + 31) // 32 * 32
+        assert f(n, nn) == r256(n * kp * 2) + r256(n * kp * 8), (n, nn)
+    for n, nn in [(3, 3), (3, 0), (100, 65), (2, 1), (4097, 30), (100, -1)]:
+        assert f(n, nn) == 0, (n, nn)
+    # calls on a NULL context fail cleanly, before any device work
+    for fn, args in [(aco.lib.aco_nn_attach, (None, 30, None, 0)),
+                     (aco.lib.aco_construct_nn, (None, 0)),
+                     (aco.lib.aco_solve_nn, (None, 1, 0, None, None)),
+                     (aco.lib.aco_read_nn_lists, (None, None))]:
+        assert fn(*args) == aco.ACO_ERR_INVALID
