@@ -437,8 +437,8 @@ def main():
     global SYNC_LAUNCHES
     SYNC_LAUNCHES = args.sync_launches
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(DESIGN.md describes how the path would shard)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                                   "(the design notes describe how the path would shard)"}))
         sys.exit(2)
     import torch
 

@@ -84,6 +84,17 @@ def lib():
         L.oracle_construct_ant_nn.argtypes = [c.c_int32, _f32p, _i32p, _u16p, c.c_int32,
                                               c.c_uint64, c.c_uint32, c.c_uint32, _u16p]
         L.oracle_construct_ant_nn.restype = c.c_int64
+        L.oracle_product_uniform.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, c.c_uint32,
+                                             c.c_int32]
+        L.oracle_product_uniform.restype = c.c_float
+        L.oracle_product_select.argtypes = [c.c_int32, _f32p, _u8p, _f32p]
+        L.oracle_product_select.restype = c.c_int32
+        L.oracle_product_select_batch.argtypes = [c.c_int32, c.c_int32, _f32p, _u8p, _f32p,
+                                                  _i32p]
+        L.oracle_product_select_batch.restype = None
+        L.oracle_construct_ant_product.argtypes = [c.c_int32, _f32p, _i32p, c.c_uint64,
+                                                   c.c_uint32, c.c_uint32, _u16p]
+        L.oracle_construct_ant_product.restype = c.c_int64
         L.oracle_construct.argtypes = [c.c_int32, c.c_int32, _f32p, _i32p, c.c_uint64,
                                        c.c_uint32, _u16p, _i64p]
         L.oracle_construct.restype = None
@@ -163,6 +174,57 @@ def construct_ant(choice_m: np.ndarray, dist: np.ndarray, seed: int, it: int, an
                                         np.ascontiguousarray(dist, np.int32), seed, it, ant,
                                         tour)
     return tour, int(length)
+
+
+def product_uniform(seed: int, it: int, ant: int, step: int, j: int) -> float:
+    return float(lib().oracle_product_uniform(seed, it, ant, step, j))
+
+
+def product_select(row, feasible, r) -> int:
+    row = np.ascontiguousarray(row, np.float32)
+    return int(lib().oracle_product_select(row.shape[0], row,
+                                           np.ascontiguousarray(feasible, np.uint8),
+                                           np.ascontiguousarray(r, np.float32)))
+
+
+def product_select_batch(rows, feasible, r) -> np.ndarray:
+    rows = np.ascontiguousarray(rows, np.float32)
+    count, n = rows.shape
+    out = np.empty(count, np.int32)
+    lib().oracle_product_select_batch(count, n, rows, np.ascontiguousarray(feasible, np.uint8),
+                                      np.ascontiguousarray(r, np.float32), out)
+    return out
+
+
+def construct_ant_product(choice_m, dist, seed: int, it: int, ant: int):
+    n = dist.shape[0]
+    tour = np.empty(n + 1, np.uint16)
+    length = lib().oracle_construct_ant_product(n, np.ascontiguousarray(choice_m, np.float32),
+                                                np.ascontiguousarray(dist, np.int32), seed, it,
+                                                ant, tour)
+    return tour, int(length)
+
+
+def construct_product(choice_m, dist, m: int, seed: int, it: int, threads: int = 1):
+    """All m product-rule tours of iteration ``it`` (each ant one serial call)."""
+    n = dist.shape[0]
+    tours = np.empty((m, n + 1), np.uint16)
+    lens = np.empty(m, np.int64)
+
+    def one(k):
+        t, ln = construct_ant_product(choice_m, dist, seed, it, k)
+        tours[k] = t
+        lens[k] = ln
+
+    if threads <= 1:
+        for k in range(m):
+            one(k)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, range(m)))
+    return tours, lens
 
 
 def nn_lists(dist: np.ndarray, nn: int) -> np.ndarray:
@@ -286,13 +348,16 @@ def init(dist: np.ndarray, m: int, alpha: int, beta: int, rho: float, seed: int)
 
 
 def iterate(st: OracleState, dist: np.ndarray, threads: int = 1, keep: bool = False,
-            nnl: np.ndarray | None = None):
+            nnl: np.ndarray | None = None, rule: str = "r64"):
     """One AS iteration: construct (Section II; over the candidate lists
-    ``nnl`` if given), best-so-far, update (Eqs. 2-4)."""
-    if nnl is None:
-        tours, lens = construct(st.choice, dist, st.m, st.seed, st.it, threads)
-    else:
+    ``nnl`` if given; rule "product": the product-and-argmax selection of
+    Section III-A), best-so-far, update (Eqs. 2-4)."""
+    if nnl is not None:
         tours, lens = construct_nn(st.choice, dist, nnl, st.m, st.seed, st.it, threads)
+    elif rule == "product":
+        tours, lens = construct_product(st.choice, dist, st.m, st.seed, st.it, threads)
+    else:
+        tours, lens = construct(st.choice, dist, st.m, st.seed, st.it, threads)
     best = ctypes.c_int64(st.best_len)
     who = lib().oracle_best_of(st.m, lens, ctypes.byref(best))
     if who >= 0:
@@ -308,11 +373,12 @@ def iterate(st: OracleState, dist: np.ndarray, threads: int = 1, keep: bool = Fa
 
 
 def solve(dist: np.ndarray, m: int, alpha: int, beta: int, rho: float, seed: int,
-          iters: int, threads: int = 1, keep: bool = False, nn: int | None = None) -> OracleState:
+          iters: int, threads: int = 1, keep: bool = False, nn: int | None = None,
+          rule: str = "r64") -> OracleState:
     """``iters`` iterations from the initial state; nn: candidate-list
-    construction with lists of that length."""
+    construction with lists of that length; rule: "r64" or "product"."""
     st = init(dist, m, alpha, beta, rho, seed)
     nnl = None if nn is None else nn_lists(dist, nn)
     for _ in range(iters):
-        iterate(st, dist, threads, keep, nnl)
+        iterate(st, dist, threads, keep, nnl, rule)
     return st

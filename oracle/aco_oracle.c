@@ -293,6 +293,67 @@ int64_t oracle_construct_ant_nn(int32_t n, const float* choice, const int32_t* d
     return len;
 }
 
+float oracle_product_uniform(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
+                             int32_t j) {
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {step, ant, iter, 1u + (uint32_t)j / 4u};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return oracle_uniform(out[j % 4]);
+}
+
+int32_t oracle_product_select(int32_t n, const float* row, const uint8_t* feasible,
+                              const float* r) {
+    int32_t best = -1;
+    float best_p = 0.0f;
+    for (int32_t j = 0; j < n; ++j) {
+        if (!feasible[j]) continue;
+        const float p = row[j] * r[j];
+        if (best < 0 || p > best_p) {
+            best = j;
+            best_p = p;
+        }
+    }
+    return best;
+}
+
+void oracle_product_select_batch(int32_t count, int32_t n, const float* rows,
+                                 const uint8_t* feasible, const float* r, int32_t* out) {
+    for (int32_t q = 0; q < count; ++q)
+        out[q] = oracle_product_select(n, rows + (int64_t)q * n, feasible + (int64_t)q * n,
+                                       r + (int64_t)q * n);
+}
+
+int64_t oracle_construct_ant_product(int32_t n, const float* choice, const int32_t* dist,
+                                     uint64_t seed, uint32_t iter, uint32_t ant,
+                                     uint16_t* tour) {
+    uint8_t* feasible = (uint8_t*)malloc((size_t)n);
+    float* r = (float*)malloc(sizeof(float) * (size_t)n);
+    if (!feasible || !r) {
+        free(feasible);
+        free(r);
+        return -1;
+    }
+    memset(feasible, 1, (size_t)n);
+    int32_t cur = oracle_start_city(oracle_draw(seed, iter, ant, 0), n);
+    tour[0] = (uint16_t)cur;
+    feasible[cur] = 0;
+    int64_t len = 0;
+    for (int32_t step = 1; step < n; ++step) {
+        for (int32_t j = 0; j < n; ++j) r[j] = oracle_product_uniform(seed, iter, ant, (uint32_t)step, j);
+        const int32_t next = oracle_product_select(n, choice + (int64_t)cur * n, feasible, r);
+        tour[step] = (uint16_t)next;
+        feasible[next] = 0;
+        len += dist[(int64_t)cur * n + next];
+        cur = next;
+    }
+    tour[n] = tour[0];
+    len += dist[(int64_t)cur * n + tour[0]];
+    free(feasible);
+    free(r);
+    return len;
+}
+
 void oracle_construct(int32_t n, int32_t m, const float* choice, const int32_t* dist,
                       uint64_t seed, uint32_t iter, uint16_t* tours, int64_t* lens) {
     for (int32_t k = 0; k < m; ++k)

@@ -16,8 +16,7 @@
  * Layouts: every n x n matrix is dense row-major (element (i, j) at i*n + j).
  * Tours are m rows of n+1 uint16 city indices, tour[n] == tour[0].
  *
- * Readings of the paper that are not fixed by its text (each is listed in
- * the design doc together with the reason):
+ * Readings of the paper where its text leaves a choice open:
  *   - random numbers: Philox4x32-10, key = seed, counter = (step, ant, iter, 0),
  *     word 0 only; u = (x0 >> 8) * 2^-24; start city = (x0 * n) >> 32;
  *   - the proportional rule of Eq. (1) is sampled by the "R64" roulette: a
@@ -121,6 +120,33 @@ void oracle_nn_lists(int32_t n, const int32_t* dist, int32_t nn, uint16_t* out);
 int64_t oracle_construct_ant_nn(int32_t n, const float* choice, const int32_t* dist,
                                 const uint16_t* nnl, int32_t nn, uint64_t seed, uint32_t iter,
                                 uint32_t ant, uint16_t* tour);
+
+/* The paper's data-parallel selection (Section III-A): every city j draws its
+ * own uniform r_j, the product choice[i][j] * r_j * tabu_j is formed, and the
+ * reduction returns the largest.  Reading: visited cities are excluded (not
+ * multiplied by 0, which would let them tie at 0), the product is fl32, ties
+ * go to the lowest j, and the per-tile winners compete on the same product,
+ * so tiling cannot change the result.
+ *
+ * r_j = (x >> 8) * 2^-24 with x = word (j mod 4) of Philox4x32-10 at counter
+ * (step, ant, iter, 1 + j / 4): one Philox block serves four cities, and the
+ * counters never meet those of oracle_draw (last word 0). */
+float oracle_product_uniform(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
+                             int32_t j);
+
+/* argmax over feasible j of fl32(row[j] * r[j]), lowest j among equal
+ * products; -1 if no city is feasible. */
+int32_t oracle_product_select(int32_t n, const float* row, const uint8_t* feasible,
+                              const float* r);
+
+/* count independent selections: rows count*n, feasible count*n, r count*n. */
+void oracle_product_select_batch(int32_t count, int32_t n, const float* rows,
+                                 const uint8_t* feasible, const float* r, int32_t* out);
+
+/* One ant's tour with the product rule; placement as oracle_construct_ant. */
+int64_t oracle_construct_ant_product(int32_t n, const float* choice, const int32_t* dist,
+                                     uint64_t seed, uint32_t iter, uint32_t ant,
+                                     uint16_t* tour);
 
 /* dep_k = fl32(1 / C^k), Eq. (4) with Q = 1. */
 float oracle_deposit_amount(int64_t len);

@@ -555,6 +555,122 @@ def test_nn_tours_are_permutations(oracle_lib, n, nn):
         assert lens[k] == tour_length(d, t)
 
 
+# ----------------------------------------------------------------- product-and-argmax rule
+def test_product_uniform_matches_rocrand(oracle_lib, tmp_path_factory):
+    """r_j is word j mod 4 of Philox at counter (step, ant, iter, 1 + j / 4),
+    checked against rocRAND's own engine (run, not copied)."""
+    cases = [(1, 0, 0, 1, 0), (1, 0, 0, 1, 3), (7, 3, 11, 5, 4), (2**40 + 5, 9, 65534, 4095, 4095),
+             (3, 2, 1, 7, 2398), (3, 2, 1, 7, 2399), (99, 1, 2, 3, 17)]
+    vecs = [[seed & 0xFFFFFFFF, seed >> 32, step, ant, it, 1 + j // 4]
+            for seed, it, ant, step, j in cases]
+    ref = _rocrand_ref(tmp_path_factory, vecs)
+    for (seed, it, ant, step, j), words in zip(cases, ref):
+        want = (words[j % 4] >> 8) * 2.0**-24
+        assert oracle_lib.product_uniform(seed, it, ant, step, j) == want
+
+
+def test_product_select_ties_exclusions_rounding(oracle_lib):
+    sel = oracle_lib.product_select
+    f32 = lambda *v: np.array(v, np.float32)
+    # equal products: the lowest index
+    assert sel(f32(2, 1), [1, 1], f32(0.25, 0.5)) == 0
+    assert sel(f32(1, 2, 1), [0, 1, 1], f32(0.5, 0.25, 0.5)) == 1
+    # a visited city never wins, however large its product
+    assert sel(f32(100, 1, 2), [0, 1, 1], f32(0.9, 0.1, 0.01)) == 1
+    # all feasible products zero: the lowest feasible city
+    assert sel(f32(5, 0, 3, 0), [0, 1, 1, 1], f32(0.5, 0.5, 0.0, 0.5)) == 1
+    assert sel(f32(1, 1), [0, 0], f32(0.5, 0.5)) == -1
+    # the comparison is on binary32 products: exact products that differ but
+    # round to the same binary32 value tie, and the lowest index wins
+    w0, r0 = 1.0 + 2.0**-23, 1.0 - 2.0**-23          # exact product 1 - 2^-46
+    w1, r1 = 1.0 + 2.0**-23, 1.0 - 2.0**-24          # exact product 1 + 2^-24 - 2^-47
+    p0 = nearest_f32(Fraction(w0) * Fraction(r0))
+    p1 = nearest_f32(Fraction(w1) * Fraction(r1))
+    assert Fraction(w0) * Fraction(r0) < Fraction(w1) * Fraction(r1)
+    assert p0 == p1
+    assert sel(f32(w0, w1), [1, 1], f32(r0, r1)) == 0
+    assert sel(f32(w1, w0), [1, 1], f32(r1, r0)) == 0
+
+
+def _argmax_win_probabilities(w):
+    """P(j has the largest w_j r_j) for independent uniform r: the integral
+    over x of prod_{k != j} min(1, w_j x / w_k)."""
+    from scipy import integrate
+
+    w = np.asarray(w, np.float64)
+    probs = []
+    for j in range(len(w)):
+        f = lambda x: np.prod([min(1.0, w[j] * x / w[k]) for k in range(len(w)) if k != j])
+        pts = sorted({min(1.0, w[k] / w[j]) for k in range(len(w)) if k != j})
+        probs.append(integrate.quad(f, 0.0, 1.0, points=pts, limit=200)[0])
+    return np.array(probs)
+
+
+def test_product_win_probabilities_two_cities(oracle_lib):
+    """n = 3: after the start, two cities remain and the one with weight a
+    beats weight b >= a with probability a / (2 b)."""
+    choice = np.array([[0, 1, 3], [2, 0, 5], [4, 4, 0]], np.float32)
+    d = np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]], np.int32)
+    tours, _ = oracle_lib.construct_product(choice, d, 30000, 5, 0, threads=4)
+    for s, (a, b) in [(0, (1, 2)), (1, (0, 2)), (2, (0, 1))]:
+        sec = tours[tours[:, 0] == s, 1]
+        wa, wb = float(choice[s, a]), float(choice[s, b])
+        pa = wa / (2 * wb) if wa <= wb else 1 - wb / (2 * wa)
+        k = int((sec == a).sum())
+        assert stats.binomtest(k, len(sec), pa).pvalue > 1e-4, (s, k, len(sec), pa)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_product_win_probabilities_many_cities(oracle_lib, seed):
+    """Second-city frequencies against the exact argmax probabilities; they
+    differ from Eq. (1)'s proportional ones, which the test also shows."""
+    n = 6
+    rng = np.random.default_rng(seed)
+    choice = rng.integers(1, 9, size=(n, n)).astype(np.float32)
+    np.fill_diagonal(choice, 0)
+    d = np.ones((n, n), np.int32)
+    np.fill_diagonal(d, 0)
+    tours, _ = oracle_lib.construct_product(choice, d, 36000, seed, 0, threads=4)
+    far_from_eq1 = 0
+    for s in range(n):
+        others = [j for j in range(n) if j != s]
+        p = _argmax_win_probabilities(choice[s, others])
+        sec = tours[tours[:, 0] == s, 1]
+        obs = np.array([(sec == j).sum() for j in others])
+        assert abs(p.sum() - 1.0) < 1e-9
+        assert stats.chisquare(obs, p / p.sum() * obs.sum()).pvalue > 1e-4, s
+        q = choice[s, others].astype(np.float64) / choice[s, others].astype(np.float64).sum()
+        far_from_eq1 += stats.chisquare(obs, q * obs.sum()).pvalue < 1e-6
+    assert far_from_eq1 >= 4
+
+
+def test_product_alpha_beta_zero_uniform_second_city(oracle_lib):
+    """alpha = beta = 0: every product is a plain uniform, so every
+    unvisited city is equally likely."""
+    n = 6
+    _, d = tsp_inputs.instance(n, "uniform", side=100, seed=4)
+    st = oracle_lib.init(d, 1, 0, 0, 0.5, 1)
+    tours, _ = oracle_lib.construct_product(st.choice, d, 12000, 5, 0, threads=4)
+    counts = np.zeros((n, n), np.int64)
+    for t in tours:
+        counts[t[0], t[1]] += 1
+    for s in range(n):
+        assert counts[s, s] == 0
+        assert stats.chisquare(np.delete(counts[s], s)).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("n,m", [(3, 4), (9, 9), (64, 10), (65, 7), (130, 5)])
+def test_product_tours_are_permutations(oracle_lib, n, m):
+    _, d = tsp_inputs.instance(n, "cluster", side=5000, seed=n)
+    st = oracle_lib.init(d, m, 1, 2, 0.5, 3)
+    tours, lens = oracle_lib.construct_product(st.choice, d, m, 3, 1)
+    for k in range(m):
+        t = tours[k]
+        assert sorted(t[:-1].tolist()) == list(range(n)) and t[n] == t[0]
+        assert t[0] == oracle_lib.start_city(oracle_lib.draw(3, 1, k, 0), n)
+        assert lens[k] == tour_length(d, t)
+
+
 # ----------------------------------------------------------------- update (C9-C11)
 def test_evaporation_closed_form(oracle_lib):
     """Cells no tour touches follow tau0 * (1 - rho)^k (Eq. 2)."""

@@ -7,7 +7,7 @@ integer distance matrix both sides consume.
 
 The paper measures on TSPLIB instances (att48 ... pr2392) that are not
 available here; these synthetic layouts stand in for them at the same sizes
-(n = 100, 1000, 2400) with m = n ants, as listed in the design doc.
+(n = 100, 1000, 2400) with m = n ants.
 
 * ``uniform_cities``   -- distinct integer points uniform in [0, side]^2.
 * ``clustered_cities`` -- 20 Gaussian clusters, sigma = 2% of the side,
