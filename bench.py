@@ -294,6 +294,92 @@ def bench_nn(torch, aco, d, m: int, nn: int, steps: int, warmup: int, update: st
     return out
 
 
+def philox_ceiling(torch, aco, waves_list, steps: int = 200):
+    """Philox blocks/s of aco_probe_philox for each wavefront count."""
+    out = []
+    for waves in waves_list:
+        sink = torch.zeros(waves * 64, dtype=torch.int32, device="cuda")
+        aco.probe_philox(waves, 5, 1, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        aco.probe_philox(waves, steps, 1, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(round(waves * 64 * 10 * steps / (e0.elapsed_time(e1) * 1e-3), 1))
+    return out
+
+
+def bench_product(torch, aco, d, m: int, steps: int, warmup: int, update: str, cpu_s: float):
+    """The paper's product-and-argmax construction on the same instance:
+    `steps` iterations timed like the main loop, HIP events around each
+    construction."""
+    n = d.shape[0]
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=False)
+    stream = torch.cuda.current_stream()
+    it = 0
+    for _ in range(warmup):
+        col.construct_product(it)
+        launched(torch)
+        col.update(update)
+        launched(torch)
+        it += 1
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[2 * s].record(stream)
+        col.construct_product(it)
+        launched(torch)
+        ev[2 * s + 1].record(stream)
+        col.update(update)
+        launched(torch)
+        it += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_con = float(np.mean([ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(steps)]))
+    tours, _ = col.tours()
+    best = col.best()[1]
+    col.close()
+    ant_steps = m * (n - 1)
+    blocks = ant_steps * ((n + 3) // 4)          # Philox blocks the rule needs
+    ceiling = philox_ceiling(torch, aco, [16 * 1024, m])
+    out = {
+        "ms_per_step": round(wall * 1e3 / steps, 4),
+        "value": round(ant_steps / wall * steps, 1),
+        "unit": "ant-steps/s",
+        "construct_ms": round(t_con, 4),
+        "construct_ant_steps_per_s": round(ant_steps / (t_con * 1e-3), 1),
+        "philox_blocks_per_launch": int(blocks),
+        "philox_blocks_per_s": round(blocks / (t_con * 1e-3), 1),
+        "construct_GBps": round(4 * n * ant_steps / (t_con * 1e-3) / 1e9, 1),
+        "best_len_after_run": int(best),
+        "roofline": {"bound": "alu", "achieved": round(blocks / (t_con * 1e-3), 1),
+                     "peak": ceiling[0], "unit": "Philox4x32-10 blocks/s",
+                     "frac": round(blocks / (t_con * 1e-3) / ceiling[0], 4),
+                     "peak_note": "measured: aco_probe_philox, the same Philox formulation with "
+                                  "no loads or selection, 16 wavefronts per SIMD",
+                     "ceiling_at_m_wavefronts": ceiling[1],
+                     "kernel": "k_construct_product"},
+    }
+    if not (tours < n).all():
+        out["error"] = "a tour holds a city index >= n"
+    if cpu_s > 0:
+        import oracle
+
+        st = oracle.init(d, m, ALPHA, BETA, RHO, 1)
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < cpu_s:
+            oracle.construct_ant_product(st.choice, d, 1, 0, k)
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(k * (n - 1) / el, 1), "unit": "ant-steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{k} ants of iteration 0, one by one"}
+    return out
+
+
 def bench_batch(args, torch, aco):
     """256 independent instances, n = round(exp(U(ln 50, ln 1000))), m = n,
     uniform cities, alpha 1, beta 2, rho 0.5, 25 iterations each, tiles from
@@ -429,6 +515,8 @@ def main():
     ap.add_argument("--sync-launches", action="store_true",
                     help="synchronise with the host after every launch (for profiled runs; "
                          "ms_per_step then includes the round trips)")
+    ap.add_argument("--no-product", action="store_true",
+                    help="skip the product-and-argmax construction block")
     ap.add_argument("--nn", type=int, default=30,
                     help="also time candidate-list construction with lists of this length "
                          "(0 skips it)")
@@ -507,6 +595,11 @@ def main():
     col.close()
 
     probe = None if args.no_probe else probe_bandwidth(torch, aco, n, m)
+    product_rec = None
+    if not args.no_product:
+        log("bench: product-and-argmax construction")
+        product_rec = bench_product(torch, aco, d, m, K, args.warmup, args.update,
+                                    min(3.0, args.cpu_seconds))
     nn_rec = None
     if args.nn > 0:
         log(f"bench: candidate-list construction, nn={args.nn}")
@@ -567,6 +660,7 @@ def main():
         "cpu_baseline": cpu,
         "probe": probe,
         "nn_list": nn_rec,
+        "product": product_rec,
     }
     print(json.dumps(rec), flush=True)
 

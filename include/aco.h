@@ -126,6 +126,25 @@ aco_status aco_update(aco_ctx* c, aco_update_kind kind);
 aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind,
                      uint16_t* best_tour_host, int64_t* best_len_host);
 
+/* ---- the paper's product-and-argmax selection --------------------------- */
+
+/* Construction with the data-parallel selection of Section III-A: at city i
+ * every unvisited city j draws its own uniform r_j and the next city is the
+ * unvisited j with the largest fl32(choice[i][j] * r_j), lowest j among equal
+ * products (visited cities take no part; the tiles' winners compete on the
+ * same product, so the tiling cannot change the result).  r_j = (x >> 8) *
+ * 2^-24 with x = word (j mod 4) of Philox4x32-10, key = seed, counter
+ * (step, ant, iter, 1 + j / 4); the start city is drawn as for aco_construct.
+ * This is not a sample of Eq. (1): the win probabilities differ from the
+ * proportional ones.  Tours, lengths, deposits and the update are those of
+ * aco_construct / aco_update.  Asynchronous. */
+aco_status aco_construct_product(aco_ctx* c, uint32_t iter);
+
+/* aco_solve with aco_construct_product in place of aco_construct.
+ * Synchronous. */
+aco_status aco_solve_product(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                             uint16_t* best_tour_host, int64_t* best_len_host);
+
 /* ---- nearest-neighbour candidate lists --------------------------------- */
 
 /* Construction over candidate lists (Section II: the ant chooses among the
@@ -173,7 +192,8 @@ aco_status aco_read_choice(aco_ctx* c, float* choice_host);
 aco_status aco_read_best(aco_ctx* c, uint16_t* best_tour_host, int64_t* best_len_host);
 
 /* Checkpoint restore: replaces tau with the host copy (n*n row-major, e.g.
- * from aco_read_tau), recomputes choice, and sets the iteration counter and
+ * from aco_read_tau; every value in [0, 1e18], else ACO_ERR_INVALID, which
+ * keeps every choice value finite), recomputes choice, and sets the iteration counter and
  * best-so-far length (best tour cleared if best_len < 0).  Because every
  * random number is keyed by (seed, iter, ant, step), a resumed run
  * reproduces the uninterrupted one.  Synchronous. */
@@ -212,6 +232,18 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len);
 aco_status aco_test_select(int32_t tile, int32_t n, int32_t count, const float* rows_dev,
                            const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
                            void* hip_stream);
+
+/* The product selection on `count` independent rows through the device code
+ * aco_construct_product uses, with the draws given instead of generated.
+ *   rows_dev      count rows of ld floats (device), ld = n rounded up to 64,
+ *                 columns n..ld-1 zero, 16-byte aligned
+ *   feasible_dev  count*n uint8 (device), non-zero = city may be chosen
+ *   u_dev         count*n floats (device): the draw of every city of the row
+ *   out_dev       count int32 (device): the chosen city, -1 if none feasible
+ * Asynchronous on hip_stream. */
+aco_status aco_test_product_select(int32_t n, int32_t count, const float* rows_dev,
+                                   const uint8_t* feasible_dev, const float* u_dev,
+                                   int32_t* out_dev, void* hip_stream);
 
 /* ---- construction tiles ------------------------------------------------ */
 
@@ -343,6 +375,14 @@ aco_status aco_server_stats(aco_server* s, int32_t* running, int32_t* initialisi
                             int32_t* finished, size_t* free_bytes, size_t* largest_free_block,
                             uint64_t* ticks);
 void aco_server_destroy(aco_server* s);
+
+/* Philox throughput probe (measurement of the product rule's compute
+ * ceiling): `waves` wavefronts each compute ten Philox4x32-10 blocks per lane
+ * per step, exactly as aco_construct_product draws a 2400-city row, for
+ * `steps` steps, with no memory traffic besides writing waves * 64 uint32
+ * to sink_dev (device).  Asynchronous on hip_stream. */
+aco_status aco_probe_philox(int32_t waves, int32_t steps, uint32_t seed, uint32_t* sink_dev,
+                            void* hip_stream);
 
 /* Random-row read probe: the access pattern of tour construction without its
  * arithmetic.  `waves` one-wavefront workgroups each read `steps` whole rows

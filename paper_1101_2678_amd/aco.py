@@ -46,6 +46,9 @@ def _load():
         "aco_update": (i32, [vp, i32]),
         "aco_solve": (i32, [vp, u32, i32, vp, vp]),
         "aco_read_tours": (i32, [vp, vp, vp]),
+        "aco_construct_product": (i32, [vp, u32]),
+        "aco_solve_product": (i32, [vp, u32, i32, vp, vp]),
+        "aco_test_product_select": (i32, [i32, i32, vp, vp, vp, vp, vp]),
         "aco_nn_workspace_bytes": (sz, [i32, i32]),
         "aco_nn_attach": (i32, [vp, i32, vp, sz]),
         "aco_construct_nn": (i32, [vp, u32]),
@@ -88,6 +91,7 @@ def _load():
         "aco_probe_copy": (i32, [vp, vp, sz, vp]),
         "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
         "aco_probe_rows": (i32, [vp, i32, i32, i32, i32, i32, vp, vp]),
+        "aco_probe_philox": (i32, [i32, i32, u32, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -166,6 +170,9 @@ class Colony:
                "aco_nn_attach")
         self.nn_workspace, self.nn = ws, int(nn)
 
+    def construct_product(self, it: int):
+        _check(lib.aco_construct_product(self._ctx, it), "aco_construct_product")
+
     def construct_nn(self, it: int):
         _check(lib.aco_construct_nn(self._ctx, it), "aco_construct_nn")
 
@@ -181,12 +188,12 @@ class Colony:
     # ---- synchronous calls
     def solve(self, iters: int, kind="gather", rule: str = "r64"):
         """rule "r64": full-row construction; "nn": candidate lists (needs
-        attach_nn)."""
-        fn = {"r64": lib.aco_solve, "nn": lib.aco_solve_nn}[rule]
+        attach_nn); "product": the paper's product-and-argmax selection."""
+        fn = {"r64": lib.aco_solve, "nn": lib.aco_solve_nn, "product": lib.aco_solve_product}[rule]
         tour = np.empty(self.n + 1, np.uint16)
         length = ctypes.c_int64()
         _check(fn(self._ctx, iters, _KIND[kind], tour.ctypes.data_as(ctypes.c_void_p),
-                  ctypes.byref(length)), "aco_solve" if rule == "r64" else "aco_solve_nn")
+                  ctypes.byref(length)), fn.__name__)
         return tour, int(length.value)
 
     def tours(self):
@@ -264,6 +271,27 @@ def test_select(rows, feasible, u, tile: int = 8, stream=None):
                                ctypes.c_void_p(feas.data_ptr()), ctypes.c_void_p(uu.data_ptr()),
                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
            "aco_test_select")
+    return out
+
+
+def test_product_select(rows, feasible, u, stream=None):
+    """Product-and-argmax selection on independent rows through the
+    construction kernel's code.  rows, u: (count, n) float32 torch tensors on
+    the GPU; feasible: (count, n) uint8.  Returns a (count,) int32 tensor."""
+    import torch
+
+    count, n = rows.shape
+    ld = (n + 63) // 64 * 64
+    padded = torch.zeros((count, ld), dtype=torch.float32, device=rows.device)
+    padded[:, :n] = rows
+    feas = feasible.to(torch.uint8).contiguous()
+    uu = u.to(torch.float32).contiguous()
+    out = torch.empty(count, dtype=torch.int32, device=rows.device)
+    _check(lib.aco_test_product_select(n, count, ctypes.c_void_p(padded.data_ptr()),
+                                       ctypes.c_void_p(feas.data_ptr()),
+                                       ctypes.c_void_p(uu.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "aco_test_product_select")
     return out
 
 
@@ -385,6 +413,13 @@ def probe_rows(mat, rows: int, ld: int, row_len: int, waves: int, steps: int, si
     _check(lib.aco_probe_rows(ctypes.c_void_p(mat.data_ptr()), rows, ld, row_len, waves, steps,
                               ctypes.c_void_p(sink.data_ptr()), _stream_handle(stream)),
            "aco_probe_rows")
+
+
+def probe_philox(waves: int, steps: int, seed: int, sink, stream=None):
+    """sink: int32/uint32 torch tensor of waves * 64 elements on the GPU."""
+    assert sink.numel() >= waves * 64
+    _check(lib.aco_probe_philox(waves, steps, seed, ctypes.c_void_p(sink.data_ptr()),
+                                _stream_handle(stream)), "aco_probe_philox")
 
 
 def probe_read(src, reps: int, sink, stream=None):

@@ -15,6 +15,7 @@
 #include "aco_host.hpp"
 #include "aco_state.hpp"
 #include "nn.hpp"
+#include "product.hpp"
 
 struct aco_ctx {
     aco::Colony col;
@@ -316,6 +317,35 @@ aco_status aco_solve(aco_ctx* c, uint32_t iters, aco_update_kind kind, uint16_t*
     return solve_with(c, iters, kind, aco_construct, best_tour_host, best_len_host);
 }
 
+aco_status aco_construct_product(aco_ctx* c, uint32_t iter) {
+    if (aco_status s = usable(c)) return s;
+    const hipError_t e = aco::launch_construct_product(c->col, iter, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "aco_construct_product");
+    c->pending = true;
+    c->pending_iter = iter;
+    return ACO_OK;
+}
+
+aco_status aco_solve_product(aco_ctx* c, uint32_t iters, aco_update_kind kind,
+                             uint16_t* best_tour_host, int64_t* best_len_host) {
+    return solve_with(c, iters, kind, aco_construct_product, best_tour_host, best_len_host);
+}
+
+aco_status aco_test_product_select(int32_t n, int32_t count, const float* rows_dev,
+                                   const uint8_t* feasible_dev, const float* u_dev,
+                                   int32_t* out_dev, void* hip_stream) {
+    if (n < 1 || n > aco::kMaxCities) return fail(ACO_ERR_INVALID, "n must be in [1, 4096]");
+    if (count < 0) return fail(ACO_ERR_INVALID, "count must be >= 0");
+    if (count > 0 && (!rows_dev || !feasible_dev || !u_dev || !out_dev))
+        return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)rows_dev % 16) != 0)
+        return fail(ACO_ERR_INVALID, "rows must be 16-byte aligned");
+    const hipError_t e = aco::launch_test_product_select(
+        n, count, rows_dev, feasible_dev, u_dev, out_dev, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_test_product_select");
+    return ACO_OK;
+}
+
 size_t aco_nn_workspace_bytes(int32_t n, int32_t nn) {
     if (n < 3 || n > aco::kMaxCities || nn < 1 || nn > aco::kMaxNn || nn > n - 1) return 0;
     return aco::nn_table_bytes(n, nn);
@@ -423,9 +453,11 @@ aco_status aco_restore(aco_ctx* c, const float* tau_host, uint32_t iter, int64_t
     if (!tau_host) return fail(ACO_ERR_INVALID, "tau_host is NULL");
     if (aco_status s = sync_ctx(c, "aco_restore")) return s;
     const aco::Colony& col = c->col;
+    // tau <= 1e18 keeps tau^2 (alpha = 2), every choice value and every
+    // product of a choice value with a draw finite
     for (size_t i = 0; i < (size_t)col.n * col.n; ++i)
-        if (!(tau_host[i] >= 0.0f) || std::isinf(tau_host[i]))
-            return fail(ACO_ERR_INVALID, "tau must be finite and non-negative");
+        if (!(tau_host[i] >= 0.0f && tau_host[i] <= 1e18f))
+            return fail(ACO_ERR_INVALID, "tau must be in [0, 1e18]");
     hipError_t e = hipMemcpy2D(col.tau, (size_t)col.ld * sizeof(float), tau_host,
                                (size_t)col.n * sizeof(float), (size_t)col.n * sizeof(float),
                                (size_t)col.n, hipMemcpyHostToDevice);
@@ -511,6 +543,16 @@ aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float
     const hipError_t e = aco::launch_probe_read(src_dev, bytes, reps, sink_dev,
                                                 static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_read");
+    return ACO_OK;
+}
+
+aco_status aco_probe_philox(int32_t waves, int32_t steps, uint32_t seed, uint32_t* sink_dev,
+                            void* hip_stream) {
+    if (waves < 0 || steps < 0) return fail(ACO_ERR_INVALID, "waves and steps must be >= 0");
+    if (waves > 0 && !sink_dev) return fail(ACO_ERR_INVALID, "NULL device pointer");
+    const hipError_t e = aco::launch_probe_philox(waves, steps, seed, sink_dev,
+                                                  static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_philox");
     return ACO_OK;
 }
 

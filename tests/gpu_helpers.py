@@ -37,15 +37,16 @@ def assert_same_f32(got, want, what: str):
 
 
 def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic"),
-                check_choice=True, nn=None):
+                check_choice=True, nn=None, rule="r64"):
     """Full parity: every iteration's tours, lengths, tau (and choice)
     bit-exact.  nn: construct over candidate lists of that length (the lists
-    themselves are compared first)."""
+    themselves are compared first); rule "product": the product-and-argmax
+    selection."""
     from paper_1101_2678_amd.aco import Colony
 
     n = dist.shape[0]
     log(f"  parity n={n} m={m} alpha={alpha} beta={beta} rho={rho} seed={seed} iters={iters} "
-        f"nn={nn}")
+        f"nn={nn} rule={rule}")
     ref = oracle.init(dist, m, alpha, beta, rho, seed)
     cols = {k: Colony(dist, m, alpha, beta, rho, seed, atomic=(k == "atomic")) for k in kinds}
     nnl = None
@@ -61,7 +62,9 @@ def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic
         if check_choice:
             assert_same_f32(col.choice(), ref.choice, f"{k} initial choice")
     for it in range(iters):
-        if nnl is None:
+        if rule == "product":
+            tours, lens = oracle.construct_product(ref.choice, dist, m, seed, it, ORACLE_THREADS)
+        elif nnl is None:
             tours, lens = oracle.construct(ref.choice, dist, m, seed, it, ORACLE_THREADS)
         else:
             tours, lens = oracle.construct_nn(ref.choice, dist, nnl, m, seed, it,
@@ -75,7 +78,9 @@ def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic
         ref.tau, ref.choice = oracle.update(ref.tau, tours, lens, dist, rho, alpha, beta)
         ref.it += 1
         for k, col in cols.items():
-            if nnl is None:
+            if rule == "product":
+                col.construct_product(it)
+            elif nnl is None:
                 col.construct(it)
             else:
                 col.construct_nn(it)

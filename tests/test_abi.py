@@ -214,3 +214,20 @@ def test_nn_workspace_and_validation(aco):
                      (aco.lib.aco_solve_nn, (None, 1, 0, None, None)),
                      (aco.lib.aco_read_nn_lists, (None, None))]:
         assert fn(*args) == aco.ACO_ERR_INVALID
+
+
+def test_product_entry_points_validate(aco):
+    """Product rule and Philox probe: bad arguments fail before device work."""
+    L = aco.lib
+    assert L.aco_construct_product(None, 0) == aco.ACO_ERR_INVALID
+    assert L.aco_solve_product(None, 1, 0, None, None) == aco.ACO_ERR_INVALID
+    sel = L.aco_test_product_select
+    assert sel(0, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID        # n < 1
+    assert sel(4097, 1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID     # n > 4096
+    assert sel(10, -1, 16, 16, 16, 16, None) == aco.ACO_ERR_INVALID      # count < 0
+    assert sel(10, 1, None, 16, 16, 16, None) == aco.ACO_ERR_INVALID     # NULL rows
+    assert sel(10, 1, 8, 16, 16, 16, None) == aco.ACO_ERR_INVALID        # misaligned rows
+    assert sel(10, 0, None, None, None, None, None) == aco.ACO_OK        # nothing to do
+    assert L.aco_probe_philox(-1, 1, 0, None, None) == aco.ACO_ERR_INVALID
+    assert L.aco_probe_philox(1, 1, 0, None, None) == aco.ACO_ERR_INVALID
+    assert L.aco_probe_philox(0, 1, 0, None, None) == aco.ACO_OK

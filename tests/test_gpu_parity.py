@@ -180,3 +180,36 @@ def test_parity_n2400_sampled():
         assert (tg[untouched] == tau_before[untouched] * np.float32(0.5)).all()
     g.close()
     a.close()
+
+
+def test_restore_resumes_bit_exact_and_validates():
+    """Checkpoint and resume: tau, best tour and iteration counter copied out
+    after 3 iterations and restored into a fresh context give the same state
+    after 2 more iterations as 5 uninterrupted ones (every draw is keyed by
+    (seed, iter, ant, step)).  Invalid tau is refused before any device work."""
+    from paper_1101_2678_amd.aco import ACO_ERR_INVALID, AcoError, Colony
+
+    _, d = tsp_inputs.instance(300, "cluster", side=100_000, seed=41)
+    full = Colony(d, 60, 1, 2, 0.5, 41, atomic=False)
+    full.solve(5, "gather")
+    part = Colony(d, 60, 1, 2, 0.5, 41, atomic=False)
+    part.solve(3, "gather")
+    tau, (bt, bl), it = part.tau(), part.best(), part.iteration
+    assert it == 3
+    resumed = Colony(d, 60, 1, 2, 0.5, 41, atomic=False)
+    resumed.restore(tau, it, bl, bt)
+    assert resumed.iteration == 3
+    assert_same_f32(resumed.choice(), part.choice(), "choice after restore")
+    resumed.solve(2, "gather")
+    assert_same_f32(resumed.tau(), full.tau(), "tau after resume")
+    assert resumed.best()[1] == full.best()[1]
+    assert (resumed.best()[0] == full.best()[0]).all()
+    for bad in (-1.0, np.nan, np.inf, 2e18):
+        t = tau.copy()
+        t[5, 7] = bad
+        with pytest.raises(AcoError) as e:
+            resumed.restore(t, 0)
+        assert e.value.status == ACO_ERR_INVALID
+    assert_same_f32(resumed.tau(), full.tau(), "tau untouched by refused restores")
+    for c in (full, part, resumed):
+        c.close()
