@@ -213,3 +213,48 @@ def test_restore_resumes_bit_exact_and_validates():
     assert_same_f32(resumed.tau(), full.tau(), "tau untouched by refused restores")
     for c in (full, part, resumed):
         c.close()
+
+
+@pytest.mark.parametrize("rule", ["r64", "nn", "product"])
+def test_max_cities_sampled(rule):
+    """n = 4096, the largest instance the library accepts (8 passes of the
+    construction tiles, 64-entry candidate lists): every tour a permutation
+    with its exact length, sampled ants equal to the oracle's."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1101_2678_amd.aco import Colony
+
+    n, m = 4096, 64
+    _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=4096)
+    c = Colony(d, m, 1, 2, 0.5, 5, atomic=False)
+    ch = c.choice()
+    if rule == "nn":
+        c.attach_nn(64)
+        nnl = oracle.nn_lists(d, 64)
+        assert (c.nn_lists() == nnl).all()
+        c.construct_nn(0)
+        ref = lambda k: oracle.construct_ant_nn(ch, d, nnl, 5, 0, k)
+    elif rule == "product":
+        c.construct_product(0)
+        ref = lambda k: oracle.construct_ant_product(ch, d, 5, 0, k)
+    else:
+        c.construct(0)
+        ref = lambda k: oracle.construct_ant(ch, d, 5, 0, k)
+    tours, lens = c.tours()
+    assert (np.sort(tours[:, :-1], axis=1) == np.arange(n, dtype=np.uint16)).all()
+    t64 = tours.astype(np.int64)
+    assert (d[t64[:, :-1], t64[:, 1:]].astype(np.int64).sum(axis=1) == lens).all()
+    sample = [0, 1, 31, 63]
+    log(f"  max cities rule={rule} ants {sample}")
+    with ThreadPoolExecutor(ORACLE_THREADS) as ex:
+        refs = list(ex.map(ref, sample))
+    for k, (t, ln) in zip(sample, refs):
+        assert (tours[k] == t).all() and lens[k] == ln, f"ant {k} differs"
+    c.close()
+
+
+def test_max_ants():
+    """m = 65535 ants, the largest colony (one workgroup per ant, the top of
+    the 16-bit ant field): every tour, length and tau bit-exact, both updates."""
+    _, d = tsp_inputs.instance(16, "uniform", side=10_000, seed=65535)
+    compare_run(d, 65535, 1, 2, 0.5, 7, iters=2)
