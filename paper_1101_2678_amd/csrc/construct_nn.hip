@@ -286,7 +286,125 @@ hipError_t launch_nn_passes(const Colony& c, const NnTables& t, uint32_t iter, h
     }
 }
 
+// The unseen city nearest to the row's city (smallest d, lowest index among
+// equal d), for a row of n <= 256 P cities: all P 16-byte loads are issued
+// before any is used; loads past the row (rounded up to 4 cities) return 0,
+// and those cities are flagged seen.  -1 if every city is seen.
+template <int P>
+__device__ __forceinline__ int nearest_unseen(const int32_t* row, int n, const uint8_t* seen,
+                                              int lane) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t*>(row), (short)0, ((n + 3) & ~3) * 4, 0x00020000);
+    u32x4 q[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+        q[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, (256 * p + 4 * lane) * 4, 0, 0);
+    uint32_t flags[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) flags[p] = reinterpret_cast<const uint32_t*>(seen)[64 * p + lane];
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t best = ~0u, best_j = ~0u;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            // distances are >= 1 and < 2^31, so ~0 never stands for a city
+            const uint32_t d = ((flags[p] >> (8 * e)) & 0xFFu) ? ~0u : q[p][e];
+            if (d < best) {
+                best = d;
+                best_j = (uint32_t)(256 * p + 4 * lane + e);
+            }
+        }
+    const uint32_t top = wave_min_u32(best);
+    const uint32_t j = wave_min_u32(best == top ? best_j : ~0u);
+    return top == ~0u ? -1 : (int)j;
+}
+
+// C_nn, the length of the nearest-neighbour tour from city 0 (ties to the
+// lowest index), and tau0 = fl32(m / C_nn).  Row i of the (d, j)-sorted lists
+// holds i's nearest cities, so its first unseen entry is the nearest unseen
+// city overall (every city off the list has a larger (d, j) key); only when
+// every entry is seen does the wave scan the whole distance row.  One
+// wavefront; the tour is kept in LDS and summed at the end.
+template <int P>
+__global__ __launch_bounds__(64) void k_nn_tour_lists(Colony c, NnTables t) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint8_t* s_seen = smem;
+    uint16_t* s_tour = reinterpret_cast<uint16_t*>(smem + kVisBytes);
+    const int lane = threadIdx.x;
+    const int n = c.n, nn = t.nn, kp = t.kp;
+    for (int w = lane; w < (int)(kVisBytes / 4); w += 64) {
+        uint32_t f = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) f |= (4 * w + b >= n || 4 * w + b == 0 ? 1u : 0u) << (8 * b);
+        reinterpret_cast<uint32_t*>(s_seen)[w] = f;
+    }
+    if (lane == 0) s_tour[0] = 0;
+    __syncthreads();
+    const int col = lane & (kp - 1);
+    const bool in_list = lane < nn;
+    int cur = 0;
+    for (int step = 1; step < n; ++step) {
+        const int city = t.nnl[(size_t)cur * kp + col];
+        const bool unseen = in_list & (s_seen[city] == 0);
+        const uint64_t live = ballot(unseen);
+        int next;
+        if (live) {
+            next = __builtin_amdgcn_readlane(city, __builtin_ctzll(live));
+        } else {
+            next = nearest_unseen<P>(c.dist + (size_t)cur * c.ld, n, s_seen, lane);
+            // n - step >= 1 cities are unseen, so next >= 0; the clamp only
+            // keeps the LDS indices in range should that ever break.
+            next = next < 0 ? 0 : next;
+        }
+        if (lane == 0) {
+            s_tour[step] = (uint16_t)next;
+            s_seen[next] = 1;
+        }
+        cur = next;
+    }
+    __syncthreads();
+    long long len = 0;
+    for (int s = lane; s < n; s += 64) {
+        const int i = s_tour[s], j = s + 1 < n ? s_tour[s + 1] : 0;
+        len += c.dist[(size_t)i * c.ld + j];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off);
+    if (lane == 0) {
+        *c.cnn = len;
+        *c.tau0 = (float)((double)c.m / (double)len);
+        *c.best_len = 0x7fffffffffffffffLL;
+    }
+}
+
+template <int P>
+hipError_t launch_nn_tour_passes(const Colony& c, const NnTables& t, hipStream_t s) {
+    if constexpr (P > kMaxCities / 256) {
+        return hipErrorInvalidValue;
+    } else {
+        if ((c.n + 255) / 256 != P) return launch_nn_tour_passes<P + 1>(c, t, s);
+        hipLaunchKernelGGL((k_nn_tour_lists<P>), dim3(1), dim3(64), construct_nn_lds(c.n), s, c,
+                           t);
+        return hipGetLastError();
+    }
+}
+
 }  // namespace
+
+hipError_t launch_nn_tour(const Colony& c, hipStream_t s) {
+    if (c.n < 2 || c.n > kMaxCities || c.mp < 32) return hipErrorInvalidValue;
+    // The successor table (n x mp uint16, mp >= 64) is not used before the
+    // first construction, so it holds the 32-entry lists meanwhile.
+    NnTables t{};
+    t.nn = c.n - 1 < 32 ? c.n - 1 : 32;
+    t.kp = 32;
+    t.nnl = c.succ;
+    t.cand = nullptr;
+    hipError_t e = launch_nn_lists(c, t, s);
+    if (e != hipSuccess) return e;
+    return launch_nn_tour_passes<1>(c, t, s);
+}
 
 size_t nn_table_bytes(int n, int nn) {
     const size_t kp = (size_t)nn_pitch(nn);

@@ -37,4 +37,10 @@ hipError_t launch_nn_lists(const Colony& c, const NnTables& t, hipStream_t s);
 // constructs the m tours of iteration `iter` with the candidate-list rule.
 hipError_t launch_construct_nn(const Colony& c, const NnTables& t, uint32_t iter, hipStream_t s);
 
+// C_nn (nearest-neighbour tour from city 0, ties to the lowest index), tau0
+// = fl32(m / C_nn) and the best-so-far reset, written to the colony.  Uses
+// the successor table as scratch for 32-entry neighbour lists, so it must run
+// before the first construction.
+hipError_t launch_nn_tour(const Colony& c, hipStream_t s);
+
 }  // namespace aco

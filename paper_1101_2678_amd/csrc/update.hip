@@ -19,6 +19,7 @@
 //           refreshes the choice matrix and clears the deposit matrix.
 #include "aco_device.hpp"
 #include "aco_state.hpp"
+#include "nn.hpp"
 
 namespace aco {
 namespace {
@@ -115,13 +116,6 @@ __global__ __launch_bounds__(256) void k_update_epilogue(Colony c) {
     dp[1] = make_double2(0.0, 0.0);
 }
 
-// ---------------------------------------------------------------------------
-// Initialisation: C_nn by the nearest-neighbour tour from city 0 (ties to the
-// lowest index), tau0 = fl32(m / C_nn).  One workgroup; each step is an
-// argmin over the unvisited cities of the current row.
-// ---------------------------------------------------------------------------
-constexpr int kNNThreads = 1024;
-
 __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
     return a < b ? a : b;
 }
@@ -132,47 +126,11 @@ __device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
     return v;
 }
 
-__global__ __launch_bounds__(kNNThreads) void k_nn_tour(Colony c) {
-    __shared__ uint8_t seen[kMaxCities];
-    __shared__ unsigned long long part[kNNThreads / 64];
-    __shared__ int s_next;
-    const int tid = threadIdx.x, n = c.n;
-    for (int j = tid; j < n; j += kNNThreads) seen[j] = (j == 0);
-    __syncthreads();
-    int cur = 0;
-    long long len = 0;
-    for (int step = 1; step < n; ++step) {
-        const int32_t* row = c.dist + (size_t)cur * c.ld;
-        unsigned long long best = ~0ull;
-        for (int j = tid; j < n; j += kNNThreads)
-            if (!seen[j])
-                best = umin64(best, ((unsigned long long)(uint32_t)row[j] << 32) | (uint32_t)j);
-        best = wave_min64(best);
-        if ((tid & 63) == 0) part[tid >> 6] = best;
-        __syncthreads();
-        if (tid < 64) {
-            unsigned long long v = (tid < kNNThreads / 64) ? part[tid] : ~0ull;
-            v = wave_min64(v);
-            if (tid == 0) {
-                // n - step >= 1 cities are unseen, so v holds one of them
-                s_next = (v == ~0ull) ? 0 : (int)(v & 0xffffffffu);
-                seen[s_next] = 1;
-            }
-        }
-        __syncthreads();
-        const int next = s_next;
-        len += row[next];
-        cur = next;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        len += c.dist[(size_t)cur * c.ld + 0];
-        *c.cnn = len;
-        *c.tau0 = (float)((double)c.m / (double)len);
-        *c.best_len = 0x7fffffffffffffffLL;
-    }
-}
-
+// ---------------------------------------------------------------------------
+// Initialisation: C_nn by the nearest-neighbour tour from city 0 (ties to the
+// lowest index) and tau0 = fl32(m / C_nn) come from launch_nn_tour
+// (construct_nn.hip); the fill below sets tau and choice.
+// ---------------------------------------------------------------------------
 // grid (ceil(ld / 4 / 256), n): tau <- tau0 (padding 0), choice from tau,
 // delta <- 0 when present.
 __global__ __launch_bounds__(256) void k_fill_init(Colony c) {
@@ -276,7 +234,8 @@ hipError_t launch_update_atomic(const Colony& c, hipStream_t s) {
 }
 
 hipError_t launch_init(const Colony& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_nn_tour, dim3(1), dim3(kNNThreads), 0, s, c);
+    const hipError_t e = launch_nn_tour(c, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_init, cell_grid(c), dim3(256), 0, s, c);
     return hipGetLastError();
 }
