@@ -116,28 +116,40 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Draws of one step from Philox: lane l's eight cities of every pass p
-// (blocks 1 + q and 2 + q, q = (512 p + 8 l) / 4).
+// Layout of a row over the W wavefronts of an ant: in pass p, lane l of wave
+// w holds cities 512 p + 64 GW w + GW l .. + GW - 1 with GW = 8 / W cities per
+// lane, so every 512-city pass is split evenly between the waves and each
+// lane's cities are GW / 4 whole Philox blocks.
+template <int W>
+struct Lay {
+    static_assert(W == 1 || W == 2, "one or two wavefronts per ant");
+    static constexpr int GW = kG / W;
+    __device__ static constexpr int city(int p, int w, int lane, int e) {
+        return kPass * p + 64 * GW * w + GW * lane + e;
+    }
+};
+
+// Draws of one step from Philox for lane `lane` of wave w: block 1 + q + b
+// holds cities 4 (q + b) .. + 3 (q = first city / 4).
 struct PhiloxDraws {
     uint32_t k0, k1, step, ant, iter;
-    template <int P>
-    __device__ __forceinline__ void get_all(int lane, float (&r)[P][kG]) const {
-        uint32_t ctr[2 * P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const uint32_t q = (uint32_t)(kPass * p + kG * lane) / 4u;
-            ctr[2 * p] = 1u + q;
-            ctr[2 * p + 1] = 2u + q;
-        }
-        u32x4 x[2 * P];
-        philox4_many<2 * P>(k0, k1, step, ant, iter, ctr, x);
+    template <int P, int W>
+    __device__ __forceinline__ void get_all(int w, int lane, float (&r)[P][Lay<W>::GW]) const {
+        constexpr int B = Lay<W>::GW / 4;  // blocks per lane per pass
+        uint32_t ctr[B * P];
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                r[p][e] = unit24(x[2 * p][e]);
-                r[p][4 + e] = unit24(x[2 * p + 1][e]);
-            }
+            for (int b = 0; b < B; ++b)
+                ctr[B * p + b] = 1u + (uint32_t)Lay<W>::city(p, w, lane, 0) / 4u + (uint32_t)b;
+        u32x4 x[B * P];
+        philox4_many<B * P>(k0, k1, step, ant, iter, ctr, x);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) r[p][4 * b + e] = unit24(x[B * p + b][e]);
     }
 };
 
@@ -145,13 +157,13 @@ struct PhiloxDraws {
 struct ArrayDraws {
     const float* u;
     int n;
-    template <int P>
-    __device__ __forceinline__ void get_all(int lane, float (&r)[P][kG]) const {
+    template <int P, int W>
+    __device__ __forceinline__ void get_all(int w, int lane, float (&r)[P][Lay<W>::GW]) const {
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int e = 0; e < kG; ++e) {
-                const int j = kPass * p + kG * lane + e;
+            for (int e = 0; e < Lay<W>::GW; ++e) {
+                const int j = Lay<W>::city(p, w, lane, e);
                 r[p][e] = j < n ? u[j] : 0.0f;
             }
     }
@@ -164,130 +176,186 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t bits, int e) {
     return m;
 }
 
-// The next city: bit kG p + e of `bits` says whether city 512 p + 8 lane + e
-// may be chosen.  Products of finite non-negative values are finite and
-// non-negative, so their bit patterns order like the values; key = bits + 1
-// (0 = no candidate in this lane).  Returns -1 if no city is feasible.
-template <int P, typename Draws>
-__device__ __forceinline__ int product_pick(const float* row, int n, uint64_t bits,
-                                            const Draws& draws, int lane) {
+// One wave's share of the selection: bit GW p + e of `bits` says whether the
+// lane's city e of pass p may be chosen.  Products of finite non-negative
+// values are finite and non-negative, so their bit patterns order like the
+// values; key = bits + 1 (0 = no candidate).  Returns the wave's largest key
+// (0 if none) and the lowest city holding it.
+struct Pick {
+    uint32_t key, city;
+};
+
+template <int P, int W, typename Draws>
+__device__ __forceinline__ Pick product_pick(const float* row, int n, uint64_t bits,
+                                             const Draws& draws, int w, int lane) {
+    constexpr int GW = Lay<W>::GW;
+    constexpr int L = GW / 4;  // 16-byte loads per lane per pass
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(row), (short)0, ((n + 3) & ~3) * 4, 0x00020000);
-    u32x4 wa[P], wb[P];
+    u32x4 wv[P][L];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const int off = (kPass * p + kG * lane) * 4;
-        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
-    }
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int b = 0; b < L; ++b)
+            wv[p][b] = __builtin_amdgcn_raw_buffer_load_b128(
+                rs, (Lay<W>::city(p, w, lane, 0) + 4 * b) * 4, 0, 0);
     // every row load above is in flight before the first draw is computed
     __builtin_amdgcn_sched_barrier(0);
-    float r[P][kG];
-    draws.template get_all<P>(lane, r);
+    float r[P][GW];
+    draws.template get_all<P, W>(w, lane, r);
     uint32_t best = 0, best_j = ~0u;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const uint32_t w[kG] = {wa[p].x, wa[p].y, wa[p].z, wa[p].w,
-                                wb[p].x, wb[p].y, wb[p].z, wb[p].w};
-        const uint32_t pass_bits = (uint32_t)(bits >> (kG * p));
+        const uint32_t pass_bits = (uint32_t)(bits >> (GW * p));
 #pragma unroll
-        for (int e = 0; e < kG; ++e) {
-            const float prod = __uint_as_float(w[e]) * r[p][e];
+        for (int e = 0; e < GW; ++e) {
+            const float prod = __uint_as_float(wv[p][e / 4][e % 4]) * r[p][e];
             const uint32_t key = (__float_as_uint(prod) + 1u) & bit_mask(pass_bits, e);
             if (key > best) {
                 best = key;
-                best_j = (uint32_t)(kPass * p + kG * lane + e);
+                best_j = (uint32_t)Lay<W>::city(p, w, lane, e);
             }
         }
     }
     const uint32_t top = wave_max_u32(best);
     const uint32_t j = wave_min_u32(best == top && best != 0u ? best_j : ~0u);
-    return top == 0u ? -1 : (int)j;
+    return Pick{top, j};
 }
 
 // Feasibility bits of a fresh tour: cities < n.
-template <int P>
-__device__ __forceinline__ uint64_t initial_bits(int n, int lane) {
+template <int P, int W>
+__device__ __forceinline__ uint64_t initial_bits(int n, int w, int lane) {
     uint64_t bits = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < kG; ++e)
-            if (kPass * p + kG * lane + e < n) bits |= 1ull << (kG * p + e);
+        for (int e = 0; e < Lay<W>::GW; ++e)
+            if (Lay<W>::city(p, w, lane, e) < n) bits |= 1ull << (Lay<W>::GW * p + e);
     return bits;
 }
 
-// Clears city j's bit in the lane that holds it.
-__device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& bits) {
+// Clears city j's bit in the lane (of the wave) that holds it.
+template <int W>
+__device__ __forceinline__ void mark_visited(int j, int w, int lane, uint64_t& bits) {
+    constexpr int GW = Lay<W>::GW;
     const int p = j / kPass, rem = j - p * kPass;
-    if (rem / kG == lane) bits &= ~(1ull << (kG * p + rem % kG));
+    const int jw = rem / (64 * GW), r2 = rem - jw * 64 * GW;
+    if (jw == w && r2 / GW == lane) bits &= ~(1ull << (GW * p + r2 % GW));
 }
 
+// Wavefronts per ant of the construction kernel (and of its verification
+// entry point).  Two waves per ant double the waves a SIMD can switch
+// between but measured no faster: the kernel is bound by the instructions
+// it issues (draws and per-city selection), which the split does not
+// reduce, so one wave per ant, without a per-step barrier, is the default.
+constexpr int kWaves = 1;
+
 template <int P>
-__global__ __launch_bounds__(64) void k_construct_product(Colony c, uint32_t iter) {
+__global__ __launch_bounds__(64 * kWaves) void k_construct_product(Colony c, uint32_t iter) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* s_tour = reinterpret_cast<uint16_t*>(smem);
-    const int lane = threadIdx.x;
+    __shared__ uint32_t s_key[2][kWaves], s_city[2][kWaves];
+    __shared__ long long s_len[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int k = blockIdx.x;
     const int n = c.n;
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
-    uint64_t bits = initial_bits<P>(n, lane);
+    uint64_t bits = initial_bits<P, kWaves>(n, w, lane);
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
-    if (lane == 0) s_tour[0] = (uint16_t)cur;
-    mark_visited(cur, lane, bits);
+    if (tid == 0) s_tour[0] = (uint16_t)cur;
+    mark_visited<kWaves>(cur, w, lane, bits);
 
     for (int step = 1; step < n; ++step) {
         const PhiloxDraws draws{key.k0, key.k1, (uint32_t)step, (uint32_t)k, iter};
-        int next = product_pick<P>(c.choice + (size_t)cur * c.ld, n, bits, draws, lane);
+        const Pick mine = product_pick<P, kWaves>(c.choice + (size_t)cur * c.ld, n, bits, draws,
+                                                  w, lane);
+        int next;
+        if constexpr (kWaves == 1) {
+            next = mine.key == 0u ? -1 : (int)mine.city;
+        } else {
+            // winners of both waves, double-buffered by step parity: a wave
+            // can rewrite a slot only after passing the next barrier, which
+            // the other wave reaches only after reading it
+            const int par = step & 1;
+            if (lane == 0) {
+                s_key[par][w] = mine.key;
+                s_city[par][w] = mine.city;
+            }
+            __syncthreads();
+            const uint32_t k0 = s_key[par][0], k1 = s_key[par][1];
+            const uint32_t top = k0 > k1 ? k0 : k1;
+            const uint32_t c0 = k0 == top ? s_city[par][0] : ~0u;
+            const uint32_t c1 = k1 == top ? s_city[par][1] : ~0u;
+            next = top == 0u ? -1 : (int)(c0 < c1 ? c0 : c1);
+        }
         // n - step >= 1 cities are unvisited, so next >= 0; the clamp only
         // keeps the LDS index in range should that ever break.
         next = next < 0 ? 0 : next;
-        if (lane == 0) s_tour[step] = (uint16_t)next;
-        mark_visited(next, lane, bits);
+        if (tid == 0) s_tour[step] = (uint16_t)next;
+        mark_visited<kWaves>(next, w, lane, bits);
         cur = next;
     }
     __syncthreads();
-    if (lane == 0) s_tour[n] = s_tour[0];
+    if (tid == 0) s_tour[n] = s_tour[0];
     __syncthreads();
 
     // Tour length C^k (int64), deposit fl32(1/C^k), tour and neighbour tables.
     long long len = 0;
-    for (int s = lane; s < n; s += 64) {
+    for (int s = tid; s < n; s += 64 * kWaves) {
         const int i = s_tour[s], j = s_tour[s + 1];
         len += c.dist[(size_t)i * c.ld + j];
         c.succ[(size_t)i * c.mp + k] = (uint16_t)j;
         c.pred[(size_t)j * c.mp + k] = (uint16_t)i;
     }
     uint16_t* trow = c.tours + (size_t)k * c.tp;
-    for (int s = lane; s <= n; s += 64) trow[s] = s_tour[s];
+    for (int s = tid; s <= n; s += 64 * kWaves) trow[s] = s_tour[s];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off);
-    if (lane == 0) {
-        c.lens[k] = len;
-        c.dep[k] = (float)(1.0 / (double)len);
+    if (lane == 0) s_len[w] = len;
+    __syncthreads();
+    if (tid == 0) {
+        long long total = 0;
+#pragma unroll
+        for (int v = 0; v < kWaves; ++v) total += s_len[v];
+        c.lens[k] = total;
+        c.dep[k] = (float)(1.0 / (double)total);
     }
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void k_test_product_select(const float* rows, int ld, int n,
-                                                            const uint8_t* feasible,
-                                                            const float* u, int32_t* out) {
-    const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kWaves) void k_test_product_select(const float* rows, int ld,
+                                                                     int n,
+                                                                     const uint8_t* feasible,
+                                                                     const float* u, int32_t* out) {
+    __shared__ uint32_t s_key[kWaves], s_city[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = blockIdx.x;
     const uint8_t* f = feasible + (size_t)q * n;
     uint64_t bits = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int e = 0; e < kG; ++e) {
-            const int j = kPass * p + kG * lane + e;
-            if (j < n && f[j]) bits |= 1ull << (kG * p + e);
+        for (int e = 0; e < Lay<kWaves>::GW; ++e) {
+            const int j = Lay<kWaves>::city(p, w, lane, e);
+            if (j < n && f[j]) bits |= 1ull << (Lay<kWaves>::GW * p + e);
         }
     const ArrayDraws draws{u + (size_t)q * n, n};
-    const int j = product_pick<P>(rows + (size_t)q * ld, n, bits, draws, lane);
-    if (lane == 0) out[q] = j;
+    const Pick mine = product_pick<P, kWaves>(rows + (size_t)q * ld, n, bits, draws, w, lane);
+    if (lane == 0) {
+        s_key[w] = mine.key;
+        s_city[w] = mine.city;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t top = 0;
+        for (int v = 0; v < kWaves; ++v) top = s_key[v] > top ? s_key[v] : top;
+        uint32_t j = ~0u;
+        for (int v = 0; v < kWaves; ++v)
+            if (s_key[v] == top && s_city[v] < j) j = s_city[v];
+        out[q] = top == 0u ? -1 : (int)j;
+    }
 }
 
 // Philox throughput probe: the draws of `steps` steps of a 2400-city row
@@ -328,8 +396,8 @@ hipError_t dispatch_passes(int n, F&& f) {
 hipError_t launch_construct_product(const Colony& c, uint32_t iter, hipStream_t s) {
     if (c.n < 1 || c.n > kMaxCities) return hipErrorInvalidValue;
     return dispatch_passes(c.n, [&]<int P>() {
-        hipLaunchKernelGGL((k_construct_product<P>), dim3(c.m), dim3(64), tour_bytes(c.n), s, c,
-                           iter);
+        hipLaunchKernelGGL((k_construct_product<P>), dim3(c.m), dim3(64 * kWaves),
+                           tour_bytes(c.n), s, c, iter);
         return hipGetLastError();
     });
 }
@@ -348,8 +416,8 @@ hipError_t launch_test_product_select(int n, int count, const float* rows,
     if (n < 1 || n > kMaxCities) return hipErrorInvalidValue;
     const int ld = (n + 63) & ~63;
     return dispatch_passes(n, [&]<int P>() {
-        hipLaunchKernelGGL((k_test_product_select<P>), dim3(count), dim3(64), 0, s, rows, ld, n,
-                           feasible, u, out);
+        hipLaunchKernelGGL((k_test_product_select<P>), dim3(count), dim3(64 * kWaves), 0, s, rows,
+                           ld, n, feasible, u, out);
         return hipGetLastError();
     });
 }
