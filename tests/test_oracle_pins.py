@@ -796,3 +796,60 @@ def test_best_of_strict_and_earliest(oracle_lib):
     assert oracle_lib.lib().oracle_best_of(5, lens, ctypes.byref(best)) == -1
     best = ctypes.c_int64(41)
     assert oracle_lib.lib().oracle_best_of(5, lens, ctypes.byref(best)) == 1
+
+
+# ----------------------------------------------------------------- arithmetic environment (C14)
+def test_build_flags_fix_the_arithmetic():
+    """Both sides are compiled without FP contraction and without fast-math;
+    the GPU side also keeps binary32 subnormals and avoids packed FP32."""
+    from paper_1101_2678_amd import _build
+
+    flags = " ".join(_build.HIP_FLAGS)
+    assert "-ffp-contract=off" in flags
+    assert "-fno-gpu-flush-denormals-to-zero" in flags
+    assert "-packed-fp32-ops" in flags and "-ffast-math" not in flags
+    src = open(os.path.join(os.path.dirname(HERE), "oracle", "__init__.py")).read()
+    assert "-ffp-contract=off" in src and "-ffast-math" not in src
+
+
+def test_oracle_does_not_depend_on_contraction(oracle_lib, tmp_path):
+    """The oracle has no same-precision a*b + c: built with contraction and
+    FMA instructions allowed it gives the same bits for construction and
+    update (so its pins do not hinge on the compiler flag)."""
+    import ctypes
+
+    cpu = open("/proc/cpuinfo").read() if os.path.exists("/proc/cpuinfo") else ""
+    if shutil.which("gcc") is None or " fma" not in cpu:
+        pytest.skip("gcc or an FMA-capable host CPU not available")
+    src = os.path.join(os.path.dirname(HERE), "oracle", "aco_oracle.c")
+    so = str(tmp_path / "liboracle_contract.so")
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=fast", "-mfma", "-fPIC", "-shared",
+                    src, "-o", so, "-lm"], check=True)
+    alt = ctypes.CDLL(so)
+    n, m = 60, 40
+    _, d = tsp_inputs.instance(n, "uniform", side=100_000, seed=12)
+    st = oracle_lib.init(d, m, 2, 3, 0.3, 9)
+    tours, lens = oracle_lib.construct(st.choice, d, m, 9, 0)
+    tau_ref, ch_ref = oracle_lib.update(st.tau, tours, lens, d, 0.3, 2, 3)
+    f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+    alt.oracle_update.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                  np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS"),
+                                  np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
+                                  np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
+                                  ctypes.c_int32, ctypes.c_int32, f32p, f32p]
+    alt.oracle_update.restype = ctypes.c_int32
+    tau_alt = st.tau.copy()
+    ch_alt = np.empty_like(ch_ref)
+    assert alt.oracle_update(n, m, np.float32(0.3), tours, lens, np.ascontiguousarray(d, np.int32),
+                             2, 3, tau_alt, ch_alt) == 0
+    assert (tau_alt.view(np.uint32) == tau_ref.view(np.uint32)).all()
+    assert (ch_alt.view(np.uint32) == ch_ref.view(np.uint32)).all()
+    alt.oracle_construct_ant.argtypes = [ctypes.c_int32, f32p,
+                                         np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS"),
+                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                         np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")]
+    alt.oracle_construct_ant.restype = ctypes.c_int64
+    for k in range(5):
+        t = np.empty(n + 1, np.uint16)
+        ln = alt.oracle_construct_ant(n, st.choice, np.ascontiguousarray(d, np.int32), 9, 0, k, t)
+        assert ln == lens[k] and (t == tours[k]).all()
