@@ -84,6 +84,42 @@ def test_instances_distinct_symmetric(layout):
     assert xy.min() >= 0 and xy.max() <= 10_000
 
 
+def test_uniform_coordinates_chi2():
+    """Uniform layout: per-axis and joint coordinate histograms are flat."""
+    xy = tsp_inputs.uniform_cities(20000, 999, seed=7)
+    for axis in (0, 1):
+        counts = np.bincount(xy[:, axis] * 10 // 1000, minlength=10)
+        assert stats.chisquare(counts).pvalue > 1e-4
+    joint = np.bincount((xy[:, 0] * 8 // 1000) * 8 + xy[:, 1] * 8 // 1000, minlength=64)
+    assert stats.chisquare(joint).pvalue > 1e-4
+
+
+def test_cluster_sigma_estimate():
+    """Clustered layout: 20 groups whose spread per axis is 2% of the side."""
+    from sklearn.cluster import KMeans
+
+    side = 1_000_000
+    xy = tsp_inputs.clustered_cities(4000, side, seed=3).astype(np.float64)
+    km = KMeans(n_clusters=20, n_init=10, random_state=0).fit(xy)
+    spread = []
+    for c in range(20):
+        pts = xy[km.labels_ == c]
+        if len(pts) > 50:
+            spread.extend(np.std(pts, axis=0))
+    assert 0.017 * side < np.median(spread) < 0.023 * side
+
+
+def test_instance_fingerprints():
+    """The seeded workloads are exactly those recorded (coordinates hashed)."""
+    import hashlib
+
+    want = json.load(open(os.path.join(HERE, "golden", "instance_hashes.json")))
+    for key, digest in want.items():
+        n, layout, side, seed = key.split("-")
+        xy, _ = tsp_inputs.instance(int(n), layout, side=int(side), seed=int(seed))
+        assert hashlib.sha256(xy.astype("<i8").tobytes()).hexdigest() == digest, key
+
+
 # ----------------------------------------------------------------- Philox (C5)
 def _rocrand_ref(tmp_path_factory, vectors):
     header = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
