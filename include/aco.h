@@ -13,6 +13,12 @@
  *     evaporation tau <- (1 - rho) tau, then every ant k deposits 1/C^k on
  *     each edge of its tour, in either a scatter-to-gather (row owner) or an
  *     atomic-deposit variant; the choice matrix is refreshed in the same pass.
+ * Two further construction rules share the update: the nearest-neighbour
+ * candidate lists of Section II (aco_construct_nn) and the paper's own
+ * data-parallel product-and-argmax selection of Section III-A
+ * (aco_construct_product).  Many instances run together through the batch
+ * API (aco_batch_*), and a continuous-batching server (aco_server_*) admits
+ * solve requests by resident footprint while others run.
  *
  * Conventions for every entry point:
  *   - Nothing throws or aborts across the ABI; every call returns aco_status.
@@ -301,6 +307,8 @@ aco_status aco_batch_read_tours(aco_batch* b, int32_t q, uint16_t* tours_host,
 aco_status aco_batch_read_tau(aco_batch* b, int32_t q, float* tau_host);
 aco_status aco_batch_get_iter(aco_batch* b, int32_t q, uint32_t* iter);
 aco_status aco_batch_sync(aco_batch* b);
+/* Waits for the batch's stream if a captured graph exists, releases the
+ * graph and the host state; never touches the workspace. */
 void aco_batch_destroy(aco_batch* b);
 
 /* Streams `bytes` (multiple of 16) from src_dev to dst_dev with 16-byte loads

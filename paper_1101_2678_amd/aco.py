@@ -146,6 +146,9 @@ class Colony:
         if nbytes == 0:
             _check(ACO_ERR_INVALID, "aco_workspace_bytes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        # the kernels use the workspace on self.stream: the caching allocator
+        # must not reuse it before the work queued there has finished
+        self.workspace.record_stream(self.stream)
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib.aco_init(ctypes.byref(self._ctx), ctypes.byref(self.params),
@@ -166,6 +169,7 @@ class Colony:
         if nbytes == 0:
             _check(ACO_ERR_INVALID, "aco_nn_workspace_bytes")
         ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        ws.record_stream(self.stream)
         _check(lib.aco_nn_attach(self._ctx, nn, ctypes.c_void_p(ws.data_ptr()), nbytes),
                "aco_nn_attach")
         self.nn_workspace, self.nn = ws, int(nn)
@@ -347,6 +351,7 @@ class Batch:
         if nbytes == 0:
             _check(ACO_ERR_INVALID, "aco_batch_workspace_bytes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace.record_stream(self.stream)
         ptrs = (ctypes.c_void_p * self.count)(*[d.ctypes.data for d in self._dists])
         self._b = ctypes.c_void_p()
         with torch.cuda.device(self.device):

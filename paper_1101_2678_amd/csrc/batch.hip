@@ -100,7 +100,10 @@ hipError_t enqueue_iterations(aco_batch* b, uint32_t iters) {
     return e;
 }
 
+// Waits for the batch's stream (a replay of the graph may still be running)
+// before releasing the graph.
 void drop_graph(aco_batch* b) {
+    if (b->exec || b->graph) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
