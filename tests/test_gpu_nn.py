@@ -132,3 +132,38 @@ def test_nn_full_size_sampled(layout):
         c.update("gather")
     assert (c.nn_lists() == nnl).all()  # the lists are never written after attach
     c.close()
+
+
+def test_nn_entry_points_validate():
+    """Misuse of the candidate-list entry points is refused with the
+    documented status and leaves the context usable."""
+    import ctypes
+
+    import torch
+    from paper_1101_2678_amd import aco
+    from paper_1101_2678_amd.aco import (ACO_ERR_INVALID, ACO_ERR_NOMEM, ACO_ERR_STATE, AcoError,
+                                         Colony)
+
+    _, d = tsp_inputs.instance(40, "uniform", side=10_000, seed=44)
+    c = Colony(d, 10, 1, 2, 0.5, 44, atomic=False)
+    with pytest.raises(AcoError) as e:
+        c.construct_nn(0)                       # no lists attached yet
+    assert e.value.status == ACO_ERR_STATE
+    with pytest.raises(AcoError) as e:
+        c.solve(1, "gather", rule="nn")
+    assert e.value.status == ACO_ERR_STATE
+    for bad in (0, 40, 65):                     # nn must be in [1, min(64, n - 1)]
+        with pytest.raises(AcoError) as e:
+            c.attach_nn(bad)
+        assert e.value.status == ACO_ERR_INVALID
+    need = aco.lib.aco_nn_workspace_bytes(40, 30)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    base = ws.data_ptr() + (-ws.data_ptr()) % 256
+    assert aco.lib.aco_nn_attach(c._ctx, 30, ctypes.c_void_p(base), need - 1) == ACO_ERR_NOMEM
+    assert aco.lib.aco_nn_attach(c._ctx, 30, ctypes.c_void_p(base + 16), need) == ACO_ERR_NOMEM
+    c.attach_nn(39)                             # the largest list for n = 40 works
+    c.construct_nn(0)
+    c.update("gather")
+    t, ln = c.tours()
+    assert (np.sort(t[:, :-1], axis=1) == np.arange(40)).all()
+    c.close()
