@@ -90,21 +90,39 @@ def traffic_from_profile():
 
 
 def cpu_baseline(d: np.ndarray, m: int, seconds: float):
-    """The oracle as it stands, one host thread: ants of iteration 0 built one
-    after another until `seconds` pass, then one update with m tours made by
-    tiling those ants (the update's cost does not depend on which tours)."""
+    """The oracle as it stands on the host's cores (up to 16 threads, the
+    host share of one GPU): ants of iteration 0, each one serial oracle call,
+    built by a pool of threads until `seconds` pass, then one update (a
+    serial oracle call) with m tours made by tiling those ants (the update's
+    cost does not depend on which tours)."""
+    import itertools
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
 
     n = d.shape[0]
     st = oracle.init(d, m, ALPHA, BETA, RHO, 1)
+    threads = max(1, min(16, os.cpu_count() or 1))
     tours, lens = [], []
+    lock = threading.Lock()
+    counter = itertools.count()
     t0 = time.perf_counter()
-    while True:
-        t, ln = oracle.construct_ant(st.choice, d, 1, 0, len(tours))
-        tours.append(t)
-        lens.append(ln)
-        if time.perf_counter() - t0 >= seconds or len(tours) >= m:
-            break
+    deadline = t0 + seconds
+
+    def worker():
+        while time.perf_counter() < deadline:
+            k = next(counter)
+            if k >= m:
+                return
+            t, ln = oracle.construct_ant(st.choice, d, 1, 0, k)   # ctypes drops the GIL
+            with lock:
+                tours.append(t)
+                lens.append(ln)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for f in [ex.submit(worker) for _ in range(threads)]:
+            f.result()
     t_construct = time.perf_counter() - t0
     k = len(tours)
     reps = (m + k - 1) // k
@@ -118,11 +136,11 @@ def cpu_baseline(d: np.ndarray, m: int, seconds: float):
     return {
         "value": m * (n - 1) / step_s,
         "unit": "ant-steps/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"{k} ants of iteration 0 at n={n} ({k * (n - 1)} ant-steps, "
-                   f"{t_construct:.1f} s) plus one full update with m={m} tours "
-                   f"({t_update:.2f} s); step time extrapolated to m={m} ants"),
+        "sample": (f"{k} ants of iteration 0 at n={n} ({k * (n - 1)} ant-steps) built by "
+                   f"{threads} threads in {t_construct:.1f} s, plus one full update with m={m} "
+                   f"tours ({t_update:.2f} s, one thread); step time extrapolated to m={m} ants"),
         "construct_ant_steps_per_s": (n - 1) / per_ant,
         "update_s": t_update,
         "step_s_extrapolated": step_s,
