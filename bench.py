@@ -70,9 +70,11 @@ def gather_bytes(n: int, m: int) -> int:
 
 
 def atomic_bytes(n: int, m: int) -> int:
-    """tours (2 m (n+1)) and deposits (4 m) read, 2 m n binary64 atomics (8 B
-    read + 8 B write each), epilogue: tau r/w, delta r/w, dist r, choice w."""
-    return 2 * m * (n + 1) + 4 * m + 2 * m * n * 16 + 32 * n * n
+    """tours (2 m (n+1)) and deposits (4 m) read, m n binary64 atomics into
+    the upper triangle (8 B read + 8 B write each); epilogue: tau r/w, dist r,
+    choice w (16 n^2) and the upper-triangle deposits read and cleared
+    (8 n^2)."""
+    return 2 * m * (n + 1) + 4 * m + m * n * 16 + 24 * n * n
 
 
 def traffic_from_profile():
@@ -240,7 +242,7 @@ def bench_nn(torch, aco, d, m: int, nn: int, steps: int, warmup: int, update: st
     `steps` iterations timed like the main loop, HIP events around each
     construction (candidate-table refresh included)."""
     n = d.shape[0]
-    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=False)
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update == "atomic"))
     col.attach_nn(nn)
     nnl = col.nn_lists()
     problem = nn_lists_problem(d, nnl)
@@ -333,7 +335,7 @@ def bench_product(torch, aco, d, m: int, steps: int, warmup: int, update: str, c
     `steps` iterations timed like the main loop, HIP events around each
     construction."""
     n = d.shape[0]
-    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=False)
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update == "atomic"))
     stream = torch.cuda.current_stream()
     it = 0
     for _ in range(warmup):
@@ -641,7 +643,7 @@ def main():
 
     cpu = None
     if args.cpu_seconds > 0:
-        log(f"bench: timing the oracle for ~{args.cpu_seconds:.0f} s on one host core")
+        log(f"bench: timing the oracle (up to ~{args.cpu_seconds:.0f} s of host work)")
         cpu = cpu_baseline(d, m, args.cpu_seconds)
 
     rec = {

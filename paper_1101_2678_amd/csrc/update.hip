@@ -14,9 +14,10 @@
 //           deposits in binary64 LDS slots, then evaporates, adds and
 //           refreshes the choice row.  No global atomics.
 //   atomic  (Section III-B, one thread per city of an ant's tour): each tour
-//           edge adds its deposit to both (i, j) and (j, i) of a binary64
-//           matrix with global atomics; an epilogue pass evaporates, adds,
-//           refreshes the choice matrix and clears the deposit matrix.
+//           edge adds its deposit with one global binary64 atomic to the
+//           upper-triangle cell of its undirected edge; an epilogue over
+//           pairs of 64 x 64 tiles evaporates, adds the sum to both (i, j)
+//           and (j, i), refreshes the choice matrix and clears the deposits.
 #include "aco_device.hpp"
 #include "aco_state.hpp"
 #include "nn.hpp"
@@ -82,38 +83,101 @@ __global__ __launch_bounds__(kRowThreads) void k_update_gather_batch(
     gather_row(c, (int)(e & 0xffffu), s_D);
 }
 
-// grid (ceil(n / 256), m): thread (s, k) deposits edge (tour_k[s], tour_k[s+1]).
+// grid (ceil(n / 256), m): thread (s, k) adds ant k's deposit for the tour
+// edge {tour_k[s], tour_k[s+1]}.  On a symmetric instance (i, j) and (j, i)
+// receive the same sum, so one binary64 atomic into the upper-triangle cell
+// delta[min][max] stands for both; the epilogue reads it for both cells.
 __global__ __launch_bounds__(256) void k_deposit_atomic(Colony c) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y;
     if (s >= c.n) return;
     const uint16_t* t = c.tours + (size_t)k * c.tp;
     const int i = t[s], j = t[s + 1];
-    const double d = (double)c.dep[k];
-    unsafeAtomicAdd(&c.delta[(size_t)i * c.ld + j], d);
-    unsafeAtomicAdd(&c.delta[(size_t)j * c.ld + i], d);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    unsafeAtomicAdd(&c.delta[(size_t)lo * c.ld + hi], (double)c.dep[k]);
 }
 
-// grid (ceil(ld / 4 / 256), n): evaporate + deposit + choice, clear delta.
+constexpr int kTile = 64;
+
+// Tile pair (I, J) = (blockIdx.y, blockIdx.x), I <= J, of 64 x 64 cells
+// (grid ld/64 x ld/64; pairs with I > J exit at once).  The upper-triangle
+// deposits of tile (I, J) are staged in LDS (rows beyond n as zeros); tau and
+// choice of tile (I, J) take them as they are, those of tile (J, I) take them
+// transposed (in a diagonal tile the lower cells read the upper ones), so
+// every cell gets the sum of its undirected edge; then the staged cells are
+// cleared.  Every global access is a contiguous row segment.
 __global__ __launch_bounds__(256) void k_update_epilogue(Colony c) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    const int i = blockIdx.y;
-    if (q >= c.ld / 4) return;
-    const size_t off = (size_t)i * c.ld + 4 * (size_t)q;
-    float4 t = *reinterpret_cast<float4*>(c.tau + off);
-    const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
-    double2* dp = reinterpret_cast<double2*>(c.delta + off);
-    const double2 d01 = dp[0], d23 = dp[1];
+    __shared__ double s_d[kTile][kTile + 1];
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (I > J) return;
+    const int tid = threadIdx.x;
+    const int rr = tid / 16, c0 = (tid % 16) * 4;  // rows rr + 16 q, columns c0 .. c0 + 3
     const float keep = evaporation_keep(c.rho);
-    float4 ch;
-    apply_cell(t.x, ch.x, d.x, d01.x, keep, c.alpha, c.beta);
-    apply_cell(t.y, ch.y, d.y, d01.y, keep, c.alpha, c.beta);
-    apply_cell(t.z, ch.z, d.z, d23.x, keep, c.alpha, c.beta);
-    apply_cell(t.w, ch.w, d.w, d23.y, keep, c.alpha, c.beta);
-    *reinterpret_cast<float4*>(c.tau + off) = t;
-    *reinterpret_cast<float4*>(c.choice + off) = ch;
-    dp[0] = make_double2(0.0, 0.0);
-    dp[1] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = rr + 16 * q, i = I * kTile + r;
+        double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+        if (i < c.n) {
+            const double2* dp =
+                reinterpret_cast<const double2*>(c.delta + (size_t)i * c.ld + J * kTile + c0);
+            a = dp[0];
+            b = dp[1];
+        }
+        s_d[r][c0 + 0] = a.x;
+        s_d[r][c0 + 1] = a.y;
+        s_d[r][c0 + 2] = b.x;
+        s_d[r][c0 + 3] = b.y;
+    }
+    __syncthreads();
+    // tile (I, J)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = rr + 16 * q, i = I * kTile + r;
+        if (i >= c.n) continue;
+        const size_t off = (size_t)i * c.ld + J * kTile + c0;
+        float4 t = *reinterpret_cast<float4*>(c.tau + off);
+        const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
+        double D[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int col = c0 + e;
+            D[e] = (I < J || r <= col) ? s_d[r][col] : s_d[col][r];
+        }
+        float4 ch;
+        apply_cell(t.x, ch.x, d.x, D[0], keep, c.alpha, c.beta);
+        apply_cell(t.y, ch.y, d.y, D[1], keep, c.alpha, c.beta);
+        apply_cell(t.z, ch.z, d.z, D[2], keep, c.alpha, c.beta);
+        apply_cell(t.w, ch.w, d.w, D[3], keep, c.alpha, c.beta);
+        *reinterpret_cast<float4*>(c.tau + off) = t;
+        *reinterpret_cast<float4*>(c.choice + off) = ch;
+    }
+    // tile (J, I): cell (J*64 + r, I*64 + col) is the upper cell (I*64 + col, J*64 + r)
+    if (I < J) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = rr + 16 * q, i = J * kTile + r;
+            if (i >= c.n) continue;
+            const size_t off = (size_t)i * c.ld + I * kTile + c0;
+            float4 t = *reinterpret_cast<float4*>(c.tau + off);
+            const int4 d = *reinterpret_cast<const int4*>(c.dist + off);
+            float4 ch;
+            apply_cell(t.x, ch.x, d.x, s_d[c0 + 0][r], keep, c.alpha, c.beta);
+            apply_cell(t.y, ch.y, d.y, s_d[c0 + 1][r], keep, c.alpha, c.beta);
+            apply_cell(t.z, ch.z, d.z, s_d[c0 + 2][r], keep, c.alpha, c.beta);
+            apply_cell(t.w, ch.w, d.w, s_d[c0 + 3][r], keep, c.alpha, c.beta);
+            *reinterpret_cast<float4*>(c.tau + off) = t;
+            *reinterpret_cast<float4*>(c.choice + off) = ch;
+        }
+    }
+    // clear the staged upper-triangle cells
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = I * kTile + rr + 16 * q;
+        if (i >= c.n) continue;
+        double2* dp = reinterpret_cast<double2*>(c.delta + (size_t)i * c.ld + J * kTile + c0);
+        dp[0] = make_double2(0.0, 0.0);
+        dp[1] = make_double2(0.0, 0.0);
+    }
 }
 
 __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
@@ -229,7 +293,8 @@ hipError_t launch_update_gather(const Colony& c, hipStream_t s) {
 hipError_t launch_update_atomic(const Colony& c, hipStream_t s) {
     if (!c.delta) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_deposit_atomic, dim3((c.n + 255) / 256, c.m), dim3(256), 0, s, c);
-    hipLaunchKernelGGL(k_update_epilogue, cell_grid(c), dim3(256), 0, s, c);
+    const int nt = c.ld / kTile;
+    hipLaunchKernelGGL(k_update_epilogue, dim3(nt, nt), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 
