@@ -135,6 +135,14 @@ def cpu_baseline(d: np.ndarray, m: int, seconds: float):
     t_update = time.perf_counter() - t1
     per_ant = t_construct / k
     step_s = per_ant * m + t_update
+    # one host core: the same serial calls, one after another, for a quarter
+    # of the budget (at least one ant)
+    t2 = time.perf_counter()
+    solo = 0
+    while solo == 0 or (time.perf_counter() - t2 < seconds / 4 and solo < m):
+        oracle.construct_ant(st.choice, d, 1, 0, solo)
+        solo += 1
+    t_solo = time.perf_counter() - t2
     return {
         "value": m * (n - 1) / step_s,
         "unit": "ant-steps/s",
@@ -146,7 +154,20 @@ def cpu_baseline(d: np.ndarray, m: int, seconds: float):
         "construct_ant_steps_per_s": (n - 1) / per_ant,
         "update_s": t_update,
         "step_s_extrapolated": step_s,
+        "one_core_construct_ant_steps_per_s": solo * (n - 1) / t_solo,
+        "one_core_sample": f"{solo} ants of iteration 0 built one after another in {t_solo:.1f} s",
+        "cpu_model": host_cpu_model(),
     }
+
+
+def host_cpu_model() -> str:
+    """The host processor's model name and logical CPU count, as the kernel reports them."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+    except OSError:
+        return "unknown"
+    return f"{names[0]} ({len(names)} logical CPUs)" if names else "unknown"
 
 
 def probe_bandwidth(torch, aco, n: int, m: int):
