@@ -63,6 +63,19 @@ def construct_bytes(n: int, m: int) -> int:
     return 4 * n * m * (n - 1)
 
 
+def job_roofline(con_bytes: float, seconds: float, solves: int) -> dict:
+    """Whole-job bandwidth of a many-instance workload: the choice-row bytes
+    every construction of every solve must read (4 n m (n - 1) per iteration),
+    over the wall time of the job (updates, best-so-far and gaps included);
+    with the solves/s that reading them at the HBM peak alone would allow."""
+    achieved = con_bytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "scope": "whole job: construction bytes of every solve / wall time",
+            "algorithmic_bytes": int(con_bytes),
+            "hbm_bound_solves_per_s": round(solves / (con_bytes / (HBM_PEAK_GBPS * 1e9)), 3)}
+
+
 def gather_bytes(n: int, m: int) -> int:
     """tau read+write, distances read, choice write (16 n^2), the succ/pred
     neighbour tables (4 m n) and the deposits (4 m)."""
@@ -481,6 +494,8 @@ def bench_batch(args, torch, aco):
         "speedup_vs_one_per_launch": round(t_single / t_batch, 2),
         "ant_steps_per_s": round(ant_steps / t_batch, 1),
         "tiles": {"sizes": [64, 128, 256, 512, 1024], "chosen": chosen.tolist()},
+        "roofline": job_roofline(
+            float(sum(construct_bytes(int(n), int(n)) for n in sizes)) * iters, t_batch, count),
     }
     aco.set_tile(1, 4096, 8)
     print(json.dumps(rec), flush=True)
@@ -536,6 +551,8 @@ def bench_served(args, torch, aco):
         "footprint_bytes_total": int(sum(footprint)),
         "footprint_formula_12n2_2mn_total": int(sum(formula)),
         "offered_load_note": "offered load exceeds device capacity; latency grows with trace length",
+        "roofline": job_roofline(float(sum(construct_bytes(r.n, r.m) * r.iters for r in reqs)),
+                                 batched["makespan_s"], len(reqs)),
     }
     print(json.dumps(rec), flush=True)
 
