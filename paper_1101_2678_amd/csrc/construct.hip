@@ -8,6 +8,14 @@
 //     holds cities 64Gp + Gl .. 64Gp + Gl + G-1, so one pass reads 256 G bytes
 //     contiguously and every 64-city block sits in 64/G neighbouring lanes;
 //   * visited cities are masked to +0 with a per-lane bit set (bit Gp + e);
+//     with SKIP, a 16-byte load whose four cities are all visited (or beyond
+//     n) is sent to an out-of-range offset instead, which returns zeros
+//     without a memory access, so late in a tour the lines of the row that
+//     hold no unvisited city are not fetched at all.  That saves bandwidth
+//     where the launch is bandwidth-bound (rows of three or more passes, and
+//     the batched launch) but lengthens a step where it is latency-bound
+//     (one or two passes with about one wavefront per SIMD), so it is on
+//     only in the former;
 //   * the total T_b of each 64-city block is a balanced pairwise sum: log2 G
 //     levels inside the lane, log2(64/G) DPP levels across the lanes.  That
 //     is exactly the last entry of the 64-wide S64 prefix tree, so every T_b
@@ -29,6 +37,7 @@ namespace aco {
 namespace {
 
 constexpr float kBlockSlack = 1.00000095367431640625f;  // 1 + 2^-20
+constexpr int kSkipOffset = 1 << 30;  // past any row: a buffer load there returns 0
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -149,7 +158,7 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
 // is staged into LDS only when that block is scanned.  The workgroup is one
 // wavefront: its LDS operations execute in program order, and every LDS
 // access below uses a lane-dependent index, so the compiler keeps the order.
-template <int G, int P, bool GUARD>
+template <int G, int P, bool GUARD, bool SKIP>
 __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
                                         uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
                                         float* s_w, float u, int lane) {
@@ -160,9 +169,14 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, in
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (GUARD && p >= np) break;
+        const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
         const int off = (p * Tile<G>::kPass + lane * G) * 4;
-        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        if (G == 8) wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        const int oa = (!SKIP || (bits & 0xFu)) ? off : kSkipOffset;
+        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, oa, 0, 0);
+        if (G == 8) {
+            const int ob = (!SKIP || (bits & 0xF0u)) ? off + 16 : kSkipOffset;
+            wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, ob, 0, 0);
+        }
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -222,7 +236,7 @@ struct AntShared {
 
 // The whole tour of ant k of colony c in iteration `iter`: placement, n - 1
 // roulette steps, then length, deposit, tour and neighbour tables.
-template <int G, int P, bool GUARD>
+template <int G, int P, bool GUARD, bool SKIP>
 __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t iter,
                                               uint16_t* s_tour, AntShared& sh) {
     const int lane = threadIdx.x;
@@ -246,7 +260,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
         if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const float* row = c.choice + (size_t)cur * c.ld;
-        int j = r64_pick<G, P, GUARD>(row, n, np, lane_bits, sh.vis, sh.T, sh.w, u, lane);
+        int j = r64_pick<G, P, GUARD, SKIP>(row, n, np, lane_bits, sh.vis, sh.T, sh.w, u, lane);
         // At every step n - step >= 1 cities are unvisited, so j >= 0; the
         // clamp only keeps the LDS indices in range should that ever break.
         j = j < 0 ? 0 : j;
@@ -280,7 +294,7 @@ template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
     __shared__ __align__(16) AntShared sh;
-    construct_ant<G, P, false>(c, blockIdx.x, iter, s_tour, sh);
+    construct_ant<G, P, false, (P >= 3)>(c, blockIdx.x, iter, s_tour, sh);
 }
 
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
@@ -294,9 +308,9 @@ __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict
     const Colony c = cols[e >> 16];
     const uint32_t iter = *c.iter_dev;
     if (c.tile == 4)
-        construct_ant<4, 4, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+        construct_ant<4, 4, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
     else
-        construct_ant<8, 8, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+        construct_ant<8, 8, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
 }
 
 template <int G, int P>
@@ -323,8 +337,8 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
             if (j < n && f[j]) lane_bits |= 1ull << (p * G + e);
         }
     __syncthreads();
-    const int j = r64_pick<G, P, false>(rows + (size_t)q * ld, n, P, lane_bits, sh.vis, sh.T,
-                                        sh.w, us[q], lane);
+    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, n, P, lane_bits, sh.vis, sh.T,
+                                              sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
 
