@@ -41,8 +41,9 @@ constexpr int kMaxTile4Cities = 1024;  // tile 4 holds 16 passes of 256 cities a
 // for n cities.
 bool tile_supported(int tile, int n);
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
-// One workgroup per entry of antmap: (colony << 16) | ant.  max_n bounds the
-// tour kept in LDS.
+// One workgroup per entry of antmap: (colony << 16) | ant.  max_n, the largest
+// n among the colonies, sizes the tour kept in LDS and picks the kernel's
+// pass bound, so it must not be smaller than any colony's n.
 hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
                                   int max_n, hipStream_t s);
 hipError_t launch_best_batch(const Colony* cols, int count, hipStream_t s);

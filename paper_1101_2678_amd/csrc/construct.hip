@@ -300,6 +300,10 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
 // cols[antmap[g] >> 16] in that colony's current iteration (*iter_dev).  Each
 // colony carries its own tile; the pass count is read at run time (GUARD).
+// P8 bounds the passes of tile-8 colonies (every colony of the launch has
+// n <= 512 P8), so a batch of small instances holds no registers for rows it
+// does not have; tile 4 is only ever set for n <= 1024 (4 passes).
+template <int P8>
 __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict__ cols,
                                                         const uint32_t* __restrict__ antmap) {
     extern __shared__ uint16_t s_tour[];
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict
     if (c.tile == 4)
         construct_ant<4, 4, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
     else
-        construct_ant<8, 8, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+        construct_ant<8, P8, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
 }
 
 template <int G, int P>
@@ -343,6 +347,23 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
 }
 
 size_t tour_lds_bytes(int n) { return ((size_t)(n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15; }
+
+// Batched launches hold at most kBatchWgPerCu workgroups per CU, by asking
+// for more dynamic LDS than the tour needs.  Each workgroup keeps one choice
+// row in flight; with more of them the rows evict one another from the L2 of
+// each XCD.  On a 256-instance batch (n 50..1000) 20 per CU gave the highest
+// throughput: 24 and 16 were 0.5% and 1.2% slower, 32 (no cap) 4% and 12
+// 19% slower.
+constexpr int kBatchWgPerCu = 20;
+constexpr size_t kLdsPerCu = 160 * 1024;  // gfx950
+
+size_t batch_lds_bytes(int max_n) {
+    const size_t per_wg = kLdsPerCu / kBatchWgPerCu;
+    const size_t fixed = sizeof(AntShared) + 64;  // static LDS and its alignment
+    const size_t cap = (per_wg - fixed) & ~(size_t)255;
+    const size_t tour = tour_lds_bytes(max_n);
+    return tour > cap ? tour : cap;
+}
 
 // Calls f.template operator()<G, P>() for the tile and pass count of n.
 template <typename F>
@@ -400,8 +421,18 @@ hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s) {
 hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
                                   int max_n, hipStream_t s) {
     if (total_ants <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_construct_batch, dim3(total_ants), dim3(64), tour_lds_bytes(max_n), s,
-                       cols, antmap);
+    if (max_n < 1 || max_n > kMaxCities) return hipErrorInvalidValue;
+    const int passes = (max_n + 511) / 512;
+    const dim3 grid(total_ants), block(64);
+    const size_t lds = batch_lds_bytes(max_n);
+    if (passes <= 2)
+        hipLaunchKernelGGL(k_construct_batch<2>, grid, block, lds, s, cols, antmap);
+    else if (passes <= 4)
+        hipLaunchKernelGGL(k_construct_batch<4>, grid, block, lds, s, cols, antmap);
+    else if (passes <= 6)
+        hipLaunchKernelGGL(k_construct_batch<6>, grid, block, lds, s, cols, antmap);
+    else
+        hipLaunchKernelGGL(k_construct_batch<8>, grid, block, lds, s, cols, antmap);
     return hipGetLastError();
 }
 

@@ -112,6 +112,40 @@ def test_batch_matches_single(graph, tiles):
         aco.set_tile(1, 4096, 8)
 
 
+@pytest.mark.parametrize("max_n", [1024, 1025, 2048, 2049, 3072, 3073, 4096])
+def test_batch_pass_bounds(max_n):
+    """The batched kernel is instantiated for rows of at most 2, 4, 6 or 8
+    passes of 512 cities, picked from the batch's largest n: batches whose
+    largest instance sits on each side of every bound, with small tile-4
+    instances beside it, equal their standalone runs bit for bit."""
+    from paper_1101_2678_amd import aco
+    from paper_1101_2678_amd.aco import Batch, Colony
+
+    aco.set_tile(1, 200, 4)
+    try:
+        spec = [(max_n, 6, 31), (150, 40, 32), (513, 9, 33), (7, 5, 34)]
+        dists, params = [], []
+        for n, m, s in spec:
+            _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=s)
+            dists.append(d)
+            params.append(dict(m=m, alpha=1, beta=2, rho=0.5, seed=s))
+        log(f"  batch pass bound max_n={max_n}")
+        b = Batch(dists, params)
+        b.run(2, graph=False)
+        b.sync()
+        for q, (d, p) in enumerate(zip(dists, params)):
+            c = Colony(d, p["m"], p["alpha"], p["beta"], p["rho"], p["seed"], atomic=False)
+            c.solve(2, "gather")
+            ct, cl = c.tours()
+            bt, bl = b.tours(q)
+            assert (ct == bt).all() and (cl == bl).all(), f"instance {q}: tours differ"
+            assert_same_f32(b.tau(q), c.tau(), f"instance {q} tau")
+            c.close()
+        b.close()
+    finally:
+        aco.set_tile(1, 4096, 8)
+
+
 def test_batch_against_oracle():
     """A small batch checked directly against the oracle, instance by instance."""
     from paper_1101_2678_amd.aco import Batch
