@@ -116,6 +116,15 @@ def test_parity_ragged(n, m, alpha, beta, rho):
     compare_run(d, m, alpha, beta, rho, seed=n + 7, iters=3)
 
 
+@pytest.mark.parametrize("n", [1025, 1536, 1537, 2048])
+def test_parity_three_and_four_passes(n):
+    """Rows of three and four 512-city passes, where construction skips the
+    loads of city quads that are all visited: every tour, length, tau and
+    choice bit-exact over 3 iterations, both update variants."""
+    _, d = tsp_inputs.instance(n, "cluster", side=1_000_000, seed=n)
+    compare_run(d, 40, 1, 2, 0.5, seed=n + 3, iters=3)
+
+
 @pytest.mark.parametrize("layout", ["uniform", "cluster"])
 def test_parity_n1000(layout):
     """n = m = 1000, both layouts, first iterations bit-exact."""
@@ -213,6 +222,34 @@ def test_restore_resumes_bit_exact_and_validates():
     assert_same_f32(resumed.tau(), full.tau(), "tau untouched by refused restores")
     for c in (full, part, resumed):
         c.close()
+
+
+def test_call_order():
+    """An update needs a construction before it: one without, or a second
+    one after the same construction, is refused with ACO_ERR_STATE and
+    leaves the colony as it was; the sequence then goes on as normal and
+    matches the oracle."""
+    from paper_1101_2678_amd.aco import ACO_ERR_STATE, AcoError, Colony
+
+    _, d = tsp_inputs.instance(90, "uniform", side=10_000, seed=57)
+    c = Colony(d, 20, 1, 2, 0.5, 57, atomic=True)
+    tau0 = c.tau()
+    for kind in ("gather", "atomic"):
+        with pytest.raises(AcoError) as e:
+            c.update(kind)
+        assert e.value.status == ACO_ERR_STATE
+    assert_same_f32(c.tau(), tau0, "tau after refused updates")
+    c.construct(0)
+    c.update("atomic")
+    with pytest.raises(AcoError) as e:
+        c.update("gather")
+    assert e.value.status == ACO_ERR_STATE
+    c.construct(1)
+    c.update("gather")
+    st = oracle.solve(d, 20, 1, 2, 0.5, 57, 2, threads=ORACLE_THREADS)
+    assert_same_f32(c.tau(), st.tau, "tau after two iterations vs oracle")
+    assert c.iteration == 2
+    c.close()
 
 
 @pytest.mark.parametrize("rule", ["r64", "nn", "product"])
