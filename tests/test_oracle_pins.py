@@ -232,6 +232,12 @@ def test_nn_tour_ties_lowest_index(oracle_lib):
     # from 0 the tie (1,2,3,4 all at 1) goes to 1; from 1: 2 and 3 at nint(sqrt 2)=1 -> 2;
     # from 2: 4 at 1 (sqrt 2), 3 at 2 -> 4; from 4: 3 at 1 -> 3; back to 0: 1
     assert oracle_lib.nn_tour_length(d) == 1 + 1 + 1 + 1 + 1
+    # a tie that changes the length: 0=(4,2) 1=(2,5) 2=(4,5) 3=(2,4) 4=(5,3).
+    # 0->4 (nint sqrt 2 = 1), 4->2 (sqrt 5 -> 2), then 1 and 3 tie at 2 from
+    # city 2: lowest index 1 (2), 1->3 (1), 3->0 (sqrt 8 -> 3): 9; taking 3
+    # instead gives 3->1 (1), 1->0 (sqrt 13 -> 4): 10
+    d = tsp_inputs.euc2d(np.array([[4, 2], [2, 5], [4, 5], [2, 4], [5, 3]]))
+    assert oracle_lib.nn_tour_length(d) == 1 + 2 + 2 + 1 + 3
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4])
@@ -733,6 +739,39 @@ def test_evaporation_closed_form(oracle_lib):
         assert abs(got - exact) <= exact * 2 * k * U
 
 
+def test_choice_refreshed_after_update(oracle_lib):
+    """With beta = 0 the heuristic is 1 off the diagonal, so after every
+    update choice must equal tau' bit for bit (alpha = 1), or the correctly
+    rounded tau'^2 (alpha = 2); the diagonal stays 0."""
+    n = 11
+    _, d = tsp_inputs.instance(n, "uniform", side=1000, seed=12)
+    off = ~np.eye(n, dtype=bool)
+    for alpha in (1, 2):
+        st = oracle_lib.init(d, 3, alpha, 0, 0.5, 4)
+        tau = st.tau
+        for it in range(3):
+            tours, lens = oracle_lib.construct(st.choice if it == 0 else ch, d, 3, 4, it)
+            tau, ch = oracle_lib.update(tau, tours, lens, d, 0.3, alpha, 0)
+            assert (np.diag(ch) == 0).all()
+            if alpha == 1:
+                assert (ch[off].view(np.uint32) == tau[off].view(np.uint32)).all()
+            else:
+                for i, j in [(0, 1), (4, 9), (10, 2)]:
+                    t = Fraction(float(tau[i, j]))
+                    assert f32bits(ch[i, j]) == f32bits(nearest_f32(t * t))
+
+
+def test_deposit_amount_large_lengths(oracle_lib):
+    """dep = fl32(1 / (double) C^k) (Eq. 4, Q = 1) for tour lengths beyond
+    2^24, where a binary32 length would already be rounded (real lengths at
+    n = 2400 in a 10^6 square are ~5 * 10^7).  Python's division is IEEE
+    binary64; the binary32 rounding is done exactly."""
+    for L in [1, 3, 7, 2**24 - 1, 2**24 + 1, 2**24 + 3, 50_000_003, 123_456_789,
+              1_234_567_891, 2**31 + 11, 4_200_000_001, 2**40 + 1]:
+        want = nearest_f32(Fraction(1.0 / L))
+        assert f32bits(oracle_lib.deposit_amount(L)) == f32bits(want), L
+
+
 def test_deposit_exact_against_fractions(oracle_lib):
     """D_ij equals the exact rational sum of 1/C^k deposits (rounded to binary32
     per ant) over ants using edge {i,j}; sum_{i<j} D = n * sum_k dep_k."""
@@ -755,6 +794,34 @@ def test_deposit_exact_against_fractions(oracle_lib):
             assert Fraction(float(D[i, j])) == exact[i][j]
     upper = sum(Fraction(float(D[i, j])) for i in range(n) for j in range(i + 1, n))
     assert upper == n * sum(dep)
+
+
+@pytest.mark.parametrize("rho", [0.5, 0.3])
+def test_update_single_rounding_against_fractions(oracle_lib, rho):
+    """tau' = fl32(fl32(tau * fl32(1 - rho)) + D) with D the exact sum of the
+    deposits on the edge (Eqs. 2-3): every cell against exact rationals, one
+    rounding after the sum, over three iterations of a 13-ant colony."""
+    n, m = 9, 13
+    _, d = tsp_inputs.instance(n, "uniform", side=1000, seed=8)
+    st = oracle_lib.init(d, m, 1, 2, rho, 1)
+    keep = Fraction(float(nearest_f32(1 - Fraction(float(np.float32(rho))))))
+    tau, ch = st.tau, st.choice
+    for it in range(3):
+        tours, lens = oracle_lib.construct(ch, d, m, 3, it)
+        dep = [Fraction(float(nearest_f32(Fraction(1, int(L))))) for L in lens]
+        D = [[Fraction(0)] * n for _ in range(n)]
+        for k in range(m):
+            t = tours[k]
+            for s in range(n):
+                i, j = int(t[s]), int(t[s + 1])
+                D[i][j] += dep[k]
+                D[j][i] += dep[k]
+        new_tau, ch = oracle_lib.update(tau, tours, lens, d, rho, 1, 2)
+        for i in range(n):
+            for j in range(n):
+                a = Fraction(float(nearest_f32(Fraction(float(tau[i, j])) * keep)))
+                assert f32bits(new_tau[i, j]) == f32bits(nearest_f32(a + D[i][j])), (it, i, j)
+        tau = new_tau
 
 
 def test_deposit_invariant_large(oracle_lib):
