@@ -15,9 +15,10 @@
 // are issued before the first Philox block is computed, so the row streams
 // while the vector unit generates the draws; per step the kernel does n / 4
 // Philox blocks per ant and reads 4n bytes, which makes it bound by integer
-// multiply throughput rather than by memory.  Each lane keeps its first
-// maximum in increasing city order; two DPP reductions (largest product key,
-// then lowest city among the lanes holding it) give the next city.
+// multiply throughput rather than by memory.  Each lane keeps only the
+// largest product key of each pass (one max per city); a DPP reduction gives
+// the wave's largest key, a ballot per pass finds the lowest pass and lane
+// holding it, and that lane's lowest position holding it gives the city.
 #include <hip/hip_runtime.h>
 
 #include "aco_device.hpp"
@@ -179,8 +180,10 @@ __device__ __forceinline__ uint32_t bit_mask(uint32_t bits, int e) {
 // One wave's share of the selection: bit GW p + e of `bits` says whether the
 // lane's city e of pass p may be chosen.  Products of finite non-negative
 // values are finite and non-negative, so their bit patterns order like the
-// values; key = bits + 1 (0 = no candidate).  Returns the wave's largest key
-// (0 if none) and the lowest city holding it.
+// values; a city that may not be chosen gets key 0.  Returns the wave's
+// largest key and the lowest city holding it; if no product of a city that
+// may be chosen is positive, key 0 and the lowest city that may be chosen
+// (all products equal, so the lowest index wins); city ~0 if there is none.
 struct Pick {
     uint32_t key, city;
 };
@@ -203,23 +206,49 @@ __device__ __forceinline__ Pick product_pick(const float* row, int n, uint64_t b
     __builtin_amdgcn_sched_barrier(0);
     float r[P][GW];
     draws.template get_all<P, W>(w, lane, r);
-    uint32_t best = 0, best_j = ~0u;
+    uint32_t key[P][GW], pmax[P];
+    uint32_t lmax = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const uint32_t pass_bits = (uint32_t)(bits >> (GW * p));
+        uint32_t m = 0;
 #pragma unroll
         for (int e = 0; e < GW; ++e) {
             const float prod = __uint_as_float(wv[p][e / 4][e % 4]) * r[p][e];
-            const uint32_t key = (__float_as_uint(prod) + 1u) & bit_mask(pass_bits, e);
-            if (key > best) {
-                best = key;
-                best_j = (uint32_t)Lay<W>::city(p, w, lane, e);
+            key[p][e] = __float_as_uint(prod) & bit_mask(pass_bits, e);
+            m = max(m, key[p][e]);
+        }
+        pmax[p] = m;
+        lmax = max(lmax, m);
+    }
+    const uint32_t top = wave_max_u32(lmax);
+    if (top != 0u) {
+        // cities grow with (pass, lane, position): the first pass with a lane
+        // holding top, its lowest such lane, that lane's lowest position
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const uint64_t hold = ballot(pmax[p] == top);
+            if (hold) {
+                const int src = __builtin_ctzll(hold);
+                uint32_t first = 0;
+#pragma unroll
+                for (int e = GW - 1; e >= 0; --e) first = key[p][e] == top ? (uint32_t)e : first;
+                const int e = __builtin_amdgcn_readlane((int)first, src);
+                // wave-uniform; said so, or the next row's address is taken
+                // as per-lane and every load of it becomes a loop
+                const int city = __builtin_amdgcn_readfirstlane(Lay<W>::city(p, w, src, e));
+                return Pick{top, (uint32_t)city};
             }
         }
     }
-    const uint32_t top = wave_max_u32(best);
-    const uint32_t j = wave_min_u32(best == top && best != 0u ? best_j : ~0u);
-    return Pick{top, j};
+    // No positive product: the lowest city that may be chosen.  Bit GW p + e
+    // grows with the city inside a lane.
+    uint32_t low = ~0u;
+    if (bits) {
+        const int b = __builtin_ctzll(bits);
+        low = (uint32_t)Lay<W>::city(b / GW, w, lane, b % GW);
+    }
+    return Pick{0u, wave_min_u32(low)};
 }
 
 // Feasibility bits of a fresh tour: cities < n.
@@ -273,7 +302,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_construct_product(Colony c, uin
                                                   w, lane);
         int next;
         if constexpr (kWaves == 1) {
-            next = mine.key == 0u ? -1 : (int)mine.city;
+            next = mine.city == ~0u ? -1 : (int)mine.city;
         } else {
             // winners of both waves, double-buffered by step parity: a wave
             // can rewrite a slot only after passing the next barrier, which
@@ -288,7 +317,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_construct_product(Colony c, uin
             const uint32_t top = k0 > k1 ? k0 : k1;
             const uint32_t c0 = k0 == top ? s_city[par][0] : ~0u;
             const uint32_t c1 = k1 == top ? s_city[par][1] : ~0u;
-            next = top == 0u ? -1 : (int)(c0 < c1 ? c0 : c1);
+            const uint32_t j = c0 < c1 ? c0 : c1;
+            next = j == ~0u ? -1 : (int)j;
         }
         // n - step >= 1 cities are unvisited, so next >= 0; the clamp only
         // keeps the LDS index in range should that ever break.
@@ -354,7 +384,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_test_product_select(const float
         uint32_t j = ~0u;
         for (int v = 0; v < kWaves; ++v)
             if (s_key[v] == top && s_city[v] < j) j = s_city[v];
-        out[q] = top == 0u ? -1 : (int)j;
+        out[q] = j == ~0u ? -1 : (int)j;
     }
 }
 
