@@ -310,7 +310,11 @@ __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict
     __shared__ __align__(16) AntShared sh;
     const uint32_t e = antmap[blockIdx.x];
     const Colony c = cols[e >> 16];
-    const uint32_t iter = *c.iter_dev;
+    // One value for the whole workgroup.  Read through a pointer the kernel
+    // might write, it would otherwise be taken as per-lane, and with it the
+    // start city and every row address of the tour, each load of which then
+    // becomes a loop over lanes.
+    const uint32_t iter = __builtin_amdgcn_readfirstlane(*c.iter_dev);
     if (c.tile == 4)
         construct_ant<4, 4, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
     else
@@ -351,13 +355,20 @@ size_t tour_lds_bytes(int n) { return ((size_t)(n + 1) * sizeof(uint16_t) + 15) 
 // Batched launches hold at most kBatchWgPerCu workgroups per CU, by asking
 // for more dynamic LDS than the tour needs.  Each workgroup keeps one choice
 // row in flight; with more of them the rows evict one another from the L2 of
-// each XCD.  On a 256-instance batch (n 50..1000) 20 per CU gave the highest
-// throughput: 24 and 16 were 0.5% and 1.2% slower, 32 (no cap) 4% and 12
-// 19% slower.
-constexpr int kBatchWgPerCu = 20;
+// each XCD, with fewer the latency of a step is no longer covered.  On a
+// 256-instance batch (n 50..1000) 16 per CU gave the highest throughput: 18
+// and 20 were 0.7% and 0.6% slower, 24 2.5%, 32 (no cap) 8.7%, 14 2.1% and
+// 12 13.5%.
+// The cap only pays when the launch runs many rounds of workgroups anyway:
+// a launch that fits the device in a round or two would only gain a tail, so
+// it is capped only from kCapRounds rounds at the cap up.
+constexpr int kBatchWgPerCu = 16;
+constexpr int kCapRounds = 8;
+constexpr int kCus = 256;                 // MI355X
 constexpr size_t kLdsPerCu = 160 * 1024;  // gfx950
 
-size_t batch_lds_bytes(int max_n) {
+size_t batch_lds_bytes(int max_n, int total_ants) {
+    if (total_ants < kCapRounds * kBatchWgPerCu * kCus) return tour_lds_bytes(max_n);
     const size_t per_wg = kLdsPerCu / kBatchWgPerCu;
     const size_t fixed = sizeof(AntShared) + 64;  // static LDS and its alignment
     const size_t cap = (per_wg - fixed) & ~(size_t)255;
@@ -424,7 +435,7 @@ hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, in
     if (max_n < 1 || max_n > kMaxCities) return hipErrorInvalidValue;
     const int passes = (max_n + 511) / 512;
     const dim3 grid(total_ants), block(64);
-    const size_t lds = batch_lds_bytes(max_n);
+    const size_t lds = batch_lds_bytes(max_n, total_ants);
     if (passes <= 2)
         hipLaunchKernelGGL(k_construct_batch<2>, grid, block, lds, s, cols, antmap);
     else if (passes <= 4)
