@@ -156,28 +156,30 @@ hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t b
     return e;
 }
 
-// Construction tile per instance size.  Default: 8 cities per lane.
+// Construction tile per instance size.  Default: 8 cities per lane.  The
+// table is filled once, on first use, by a function-local static (thread-safe
+// initialisation); changing it while other threads read it is not supported.
 namespace {
-int8_t g_tile[kMaxCities + 1];
-bool g_tile_init = false;
-void ensure_tiles() {
-    if (g_tile_init) return;
-    for (int n = 0; n <= kMaxCities; ++n) g_tile[n] = 8;
-    g_tile_init = true;
+int8_t* tile_table() {
+    static int8_t* const table = [] {
+        static int8_t t[kMaxCities + 1];
+        for (int n = 0; n <= kMaxCities; ++n) t[n] = 8;
+        return t;
+    }();
+    return table;
 }
 }  // namespace
 
 int tile_for(int n) {
-    ensure_tiles();
-    return (n >= 0 && n <= kMaxCities) ? g_tile[n] : 8;
+    return (n >= 0 && n <= kMaxCities) ? tile_table()[n] : 8;
 }
 
 bool set_tile_range(int lo, int hi, int tile) {
-    ensure_tiles();
     if (lo < 1 || hi > kMaxCities || lo > hi) return false;
     for (int n = lo; n <= hi; ++n)
         if (!tile_supported(tile, n)) return false;
-    for (int n = lo; n <= hi; ++n) g_tile[n] = (int8_t)tile;
+    int8_t* t = tile_table();
+    for (int n = lo; n <= hi; ++n) t[n] = (int8_t)tile;
     return true;
 }
 
