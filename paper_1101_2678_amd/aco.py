@@ -36,6 +36,13 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1101_2678_amd._build` "
             "(or __graft_entry__.build()); there is no CPU fallback")
+    # libaco.so needs the HIP runtime torch ships.  Loaded before torch, the
+    # dynamic linker would take the system's copy instead (torch's directory
+    # has it under another file name), and torch would then load its own: two
+    # runtimes in one process, the library's seeing no device.  With torch
+    # loaded first, the library binds to torch's runtime.
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     c = ctypes
     vp, sz, i32, u32, i64 = c.c_void_p, c.c_size_t, c.c_int32, c.c_uint32, c.c_int64

@@ -3,6 +3,7 @@ declared in include/aco.h, and rejects invalid arguments before touching the
 device."""
 from __future__ import annotations
 
+import ast
 import ctypes
 import os
 import re
@@ -231,3 +232,21 @@ def test_product_entry_points_validate(aco):
     assert L.aco_probe_philox(-1, 1, 0, None, None) == aco.ACO_ERR_INVALID
     assert L.aco_probe_philox(1, 1, 0, None, None) == aco.ACO_ERR_INVALID
     assert L.aco_probe_philox(0, 1, 0, None, None) == aco.ACO_OK
+
+
+def test_binding_loads_torch_hip_runtime():
+    """Importing the binding before torch must not bring a second HIP runtime
+    into the process: exactly one libamdhip64 is mapped, torch's."""
+    import subprocess
+    import sys
+
+    code = ("from paper_1101_2678_amd import aco\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         check=True).stdout
+    libs = ast.literal_eval(out.strip().splitlines()[-1])
+    assert len(libs) == 1 and os.sep + "torch" + os.sep in libs[0], libs
+
