@@ -11,8 +11,18 @@ and all state are resident in HBM before timing starts.
 Prints one JSON line.  `value` is ant-steps per second of the whole step
 (m (n-1) roulette selections per step).  Extra fields: per-kernel times from
 HIP events on the launch stream, update GB/s for both variants, the roofline
-of the construction kernel, live bandwidth probes, and the oracle timed on a
-bounded sample on the host (`cpu_baseline`).
+of the construction kernel (with the counter traffic when it was taken on the
+current kernel source), live bandwidth probes, the same steps with
+candidate-list construction (`nn_list`) and with the product-and-argmax rule
+(`product`, with its own ALU roofline), and the oracle timed on a bounded
+sample on the host (`cpu_baseline`).
+
+Other workloads: `--workload n1000u|n1000c|n100` (the same line at those
+sizes), `--workload batch256` (256 uneven instances as one graph-replayed
+batch against one instance per launch; solves/s) and `--workload served` (a
+Poisson trace through the continuous-batching server against one request at
+a time; solves/s with p50 and p99).  Profiled runs add `--sync-launches`.
+The library runs on one GPU: `--gpus` other than 1 exits with a message.
 """
 from __future__ import annotations
 
