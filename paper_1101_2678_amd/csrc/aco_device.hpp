@@ -97,6 +97,17 @@ __device__ __forceinline__ float octet_pairwise(float x) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Workgroups go to the eight XCDs round-robin by index.  A construction
+// workgroup b builds ant ant_of_block(b, m), so that each XCD runs one
+// contiguous range of ants: the successor and predecessor entries of
+// neighbouring ants share cache lines, which are then written from one L2
+// instead of in eight partial copies.  A bijection on [0, m); which workgroup
+// builds an ant does not change its tour.
+__device__ __forceinline__ int ant_of_block(int b, int m) {
+    const int x = b & 7, j = b >> 3, q = m >> 3, r = m & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ float read_lane(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }

@@ -294,7 +294,7 @@ template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
     __shared__ __align__(16) AntShared sh;
-    construct_ant<G, P, false, (P >= 3)>(c, blockIdx.x, iter, s_tour, sh);
+    construct_ant<G, P, false, (P >= 3)>(c, ant_of_block(blockIdx.x, c.m), iter, s_tour, sh);
 }
 
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony

@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void k_construct_nn(Colony c, NnTables t, uint3
     uint8_t* s_vis = smem;
     uint16_t* s_tour = reinterpret_cast<uint16_t*>(smem + kVisBytes);
     const int lane = threadIdx.x;
-    const int k = blockIdx.x;
+    const int k = ant_of_block(blockIdx.x, c.m);
     const int n = c.n, nn = t.nn, kp = t.kp;
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_construct_product(Colony c, uin
     __shared__ uint32_t s_key[2][kWaves], s_city[2][kWaves];
     __shared__ long long s_len[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int k = blockIdx.x;
+    const int k = ant_of_block(blockIdx.x, c.m);
     const int n = c.n;
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
