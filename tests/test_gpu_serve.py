@@ -63,9 +63,11 @@ def test_admission_waits_for_memory():
     r2 = Request(rid=2, arrival=0.0, dist=d2, m=280, iters=5, seed=4)
     from paper_1101_2678_amd.aco import lib
 
-    head = lib.aco_server_table_bytes(4, 4096, 4096, 3)
+    classes = (512, 1024, 2048, 4096)
+    head = lib.aco_server_table_bytes(4, 4096, 4096, len(classes))
     pool = head + workspace_bytes(300, 300, atomic=False) + 4096
-    srv = Server(pool_bytes=pool, max_slots=4, max_ants=4096, max_rows=4096)
+    srv = Server(pool_bytes=pool, max_slots=4, max_ants=4096, max_rows=4096,
+                 class_max_n=classes)
     s1 = srv.submit(r1)
     assert s1 is not None
     assert srv.submit(r2) is None  # no room
