@@ -146,6 +146,46 @@ def test_batch_pass_bounds(max_n):
         aco.set_tile(1, 4096, 8)
 
 
+def test_batch256_full_size():
+    """The benchmark's batch in the benchmark's launch configuration: 256
+    instances, n = round(exp(U(ln 50, ln 1000))) from seed 4, m = n, uniform
+    cities, instance q with seed q + 1, tile 4 up to n = 256 as the tuner
+    picks, one captured graph over 2 iterations (81,903 ants per launch, so
+    the occupancy cap of long launches is in force).  Every instance's tours,
+    lengths and tau equal its standalone run; the four smallest also equal the
+    oracle."""
+    from paper_1101_2678_amd import aco
+    from paper_1101_2678_amd.aco import Batch, Colony
+
+    sizes = tsp_inputs.log_uniform_sizes(256, 50, 1000, seed=4)
+    assert int(sizes.sum()) == 81_903
+    dists = [tsp_inputs.instance(int(n), "uniform", side=1_000_000, seed=q + 1)[1]
+             for q, n in enumerate(sizes)]
+    params = [dict(m=int(n), alpha=1, beta=2, rho=0.5, seed=q + 1) for q, n in enumerate(sizes)]
+    aco.set_tile(1, 256, 4)
+    try:
+        log("  batch256 full size, graph, 2 iterations")
+        b = Batch(dists, params)
+        b.run(2, graph=True)
+        b.sync()
+        for q, (d, p) in enumerate(zip(dists, params)):
+            c = Colony(d, p["m"], 1, 2, 0.5, p["seed"], atomic=False)
+            c.solve(2, "gather")
+            ct, cl = c.tours()
+            bt, bl = b.tours(q)
+            assert (ct == bt).all() and (cl == bl).all(), f"instance {q}: tours differ"
+            assert_same_f32(b.tau(q), c.tau(), f"instance {q} tau")
+            c.close()
+        for q in np.argsort(sizes)[:4].tolist():
+            st = oracle.solve(dists[q], params[q]["m"], 1, 2, 0.5, params[q]["seed"], 2,
+                              threads=ORACLE_THREADS)
+            assert_same_f32(b.tau(q), st.tau, f"instance {q} tau vs oracle")
+            assert b.best(q)[1] == st.best_len
+        b.close()
+    finally:
+        aco.set_tile(1, 4096, 8)
+
+
 def test_batch_against_oracle():
     """A small batch checked directly against the oracle, instance by instance."""
     from paper_1101_2678_amd.aco import Batch
