@@ -51,6 +51,29 @@ def test_served_results_equal_alone():
     srv.close()
 
 
+def test_served_trace_at_benchmark_sizes():
+    """The first 30 requests of the benchmark's trace (Poisson 200/s, n
+    log-uniform in [100, 3000], both layouts, 50 iterations each, per-request
+    seeds) through the default server (size classes, 32 slots, a pool of half
+    the free memory): every best tour and length equals the request run
+    alone with a context of its own."""
+    import copy
+
+    from paper_1101_2678_amd.serve import Server, make_requests, run_open_loop, run_plain
+
+    reqs = make_requests(30, 200.0, n_lo=100, n_hi=3000, iters=50, seed=5)
+    alone = copy.deepcopy(reqs)
+    srv = Server(max_slots=32)
+    summary = run_open_loop(srv, reqs)
+    srv.close()
+    log(f"  served at benchmark sizes: {summary}")
+    assert summary["peak_running"] >= 8  # overlapping requests in several classes
+    run_plain(alone)
+    for a, b in zip(reqs, alone):
+        assert a.best_len == b.best_len, f"request {a.rid} (n={a.n}): {a.best_len} != {b.best_len}"
+        assert (a.best_tour == b.best_tour).all(), f"request {a.rid}: tours differ"
+
+
 def test_admission_waits_for_memory():
     """A pool that fits one request at a time: the second is refused until the
     first is released, and both still give their standalone results."""
