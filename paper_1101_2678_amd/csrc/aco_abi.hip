@@ -289,10 +289,9 @@ aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
         return fail(ACO_ERR_INVALID, "unknown update kind");
     if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
         return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
-    hipError_t e = aco::launch_best(c->col, c->stream);
-    if (e == hipSuccess)
-        e = (kind == ACO_UPDATE_GATHER) ? aco::launch_update_gather(c->col, c->stream)
-                                        : aco::launch_update_atomic(c->col, c->stream);
+    // the update kernels also keep the best-so-far tour
+    const hipError_t e = (kind == ACO_UPDATE_GATHER) ? aco::launch_update_gather(c->col, c->stream)
+                                                     : aco::launch_update_atomic(c->col, c->stream);
     if (e != hipSuccess) return device_fail(c, e, "aco_update");
     c->pending = false;
     c->next_iter = c->pending_iter + 1;

@@ -52,7 +52,6 @@ hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap
                                       int max_ld, hipStream_t s);
 // Construction workgroups (ants) resident per compute unit, or -1.
 int construct_occupancy(const Colony& c);
-hipError_t launch_best(const Colony& c, hipStream_t s);
 hipError_t launch_update_gather(const Colony& c, hipStream_t s);
 hipError_t launch_update_atomic(const Colony& c, hipStream_t s);
 hipError_t launch_init(const Colony& c, hipStream_t s);

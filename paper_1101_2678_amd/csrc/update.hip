@@ -38,6 +38,53 @@ __device__ __forceinline__ void apply_cell(float& tau, float& choice, int32_t d,
     choice = choice_of(tau, heur_of(d, beta), alpha);
 }
 
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Best-so-far: the shortest tour of this iteration (lowest ant index among
+// equals) replaces the stored one only if strictly shorter.
+// ---------------------------------------------------------------------------
+// NT threads, every one of the workgroup.
+template <int NT>
+__device__ __forceinline__ void best_of(const Colony& c, bool advance_iter) {
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole wavefronts, at most 16");
+    __shared__ unsigned long long part[NT / 64];
+    __shared__ unsigned long long s_win;
+    const int tid = threadIdx.x;
+    unsigned long long best = ~0ull;
+    for (int k = tid; k < c.m; k += NT)
+        best = umin64(best, ((unsigned long long)c.lens[k] << 16) | (unsigned)k);
+    best = wave_min64(best);
+    if ((tid & 63) == 0) part[tid >> 6] = best;
+    __syncthreads();
+    if (tid < 64) {
+        unsigned long long v = (tid < NT / 64) ? part[tid] : ~0ull;
+        v = wave_min64(v);
+        if (tid == 0) s_win = v;
+    }
+    __syncthreads();
+    const long long len = (long long)(s_win >> 16);
+    const int k = (int)(s_win & 0xffffu);
+    const long long prev = *c.best_len;
+    if (len < prev) {
+        const uint16_t* src = c.tours + (size_t)k * c.tp;
+        for (int s = tid; s <= c.n; s += NT) c.best_tour[s] = src[s];
+        __syncthreads();
+        if (tid == 0) *c.best_len = len;
+    }
+    // The batched path keeps each colony's iteration counter on the device,
+    // so that a captured sequence of launches advances when replayed.
+    if (advance_iter && tid == 0) *c.iter_dev += 1u;
+}
+
 // Row i of the gather update (tid in [0, kRowThreads)).
 __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) {
     const int tid = threadIdx.x;
@@ -68,8 +115,12 @@ __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) 
     }
 }
 
+// Workgroup 0 also keeps the best-so-far tour (it reads only the lengths and
+// tours of the construction, which the update does not touch), so one launch
+// serves both.
 __global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
     extern __shared__ double s_D[];  // ld binary64 accumulators
+    if (blockIdx.x == 0) best_of<kRowThreads>(c, false);
     gather_row(c, blockIdx.x, s_D);
 }
 
@@ -110,6 +161,7 @@ __global__ __launch_bounds__(256) void k_update_epilogue(Colony c) {
     __shared__ double s_d[kTile][kTile + 1];
     const int I = blockIdx.y, J = blockIdx.x;
     if (I > J) return;
+    if (I == 0 && J == 0) best_of<256>(c, false);  // as in k_update_gather
     const int tid = threadIdx.x;
     const int rr = tid / 16, c0 = (tid % 16) * 4;  // rows rr + 16 q, columns c0 .. c0 + 3
     const float keep = evaporation_keep(c.rho);
@@ -180,16 +232,6 @@ __global__ __launch_bounds__(256) void k_update_epilogue(Colony c) {
     }
 }
 
-__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
-    return a < b ? a : b;
-}
-
-__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off));
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // Initialisation: C_nn by the nearest-neighbour tour from city 0 (ties to the
 // lowest index) and tau0 = fl32(m / C_nn) come from launch_nn_tour
@@ -239,45 +281,9 @@ __global__ __launch_bounds__(256) void k_refresh_choice(Colony c) {
     *reinterpret_cast<float4*>(c.choice + off) = ch;
 }
 
-// ---------------------------------------------------------------------------
-// Best-so-far: the shortest tour of this iteration (lowest ant index among
-// equals) replaces the stored one only if strictly shorter.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void best_of(const Colony& c, bool advance_iter) {
-    __shared__ unsigned long long part[16];
-    __shared__ unsigned long long s_win;
-    const int tid = threadIdx.x;
-    unsigned long long best = ~0ull;
-    for (int k = tid; k < c.m; k += 1024)
-        best = umin64(best, ((unsigned long long)c.lens[k] << 16) | (unsigned)k);
-    best = wave_min64(best);
-    if ((tid & 63) == 0) part[tid >> 6] = best;
-    __syncthreads();
-    if (tid < 64) {
-        unsigned long long v = (tid < 16) ? part[tid] : ~0ull;
-        v = wave_min64(v);
-        if (tid == 0) s_win = v;
-    }
-    __syncthreads();
-    const long long len = (long long)(s_win >> 16);
-    const int k = (int)(s_win & 0xffffu);
-    const long long prev = *c.best_len;
-    if (len < prev) {
-        const uint16_t* src = c.tours + (size_t)k * c.tp;
-        for (int s = tid; s <= c.n; s += 1024) c.best_tour[s] = src[s];
-        __syncthreads();
-        if (tid == 0) *c.best_len = len;
-    }
-    // The batched path keeps each colony's iteration counter on the device,
-    // so that a captured sequence of launches advances when replayed.
-    if (advance_iter && tid == 0) *c.iter_dev += 1u;
-}
-
-__global__ __launch_bounds__(1024) void k_best(Colony c) { best_of(c, false); }
-
 __global__ __launch_bounds__(1024) void k_best_batch(const Colony* __restrict__ cols) {
     const Colony c = cols[blockIdx.x];
-    best_of(c, true);
+    best_of<1024>(c, true);
 }
 
 dim3 cell_grid(const Colony& c) { return dim3((c.ld / 4 + 255) / 256, c.n); }
@@ -307,11 +313,6 @@ hipError_t launch_init(const Colony& c, hipStream_t s) {
 
 hipError_t launch_refresh_choice(const Colony& c, hipStream_t s) {
     hipLaunchKernelGGL(k_refresh_choice, cell_grid(c), dim3(256), 0, s, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_best(const Colony& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, s, c);
     return hipGetLastError();
 }
 
