@@ -129,6 +129,21 @@ def workspace_bytes(n: int, m: int, alpha: int = 1, beta: int = 2, rho: float = 
     return int(lib.aco_workspace_bytes(ctypes.byref(p), 1 if atomic else 0))
 
 
+def as_dist(dist) -> np.ndarray:
+    """The distance matrix as the library takes it: square, C-contiguous
+    int32.  Integer input outside the int32 range and non-integer input are
+    refused rather than cast, so that no distance changes on the way in (the
+    library checks symmetry, the diagonal and the range itself)."""
+    a = np.asarray(dist)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("dist must be a square matrix")
+    if not np.issubdtype(a.dtype, np.integer):
+        raise TypeError(f"dist must hold integers (nint distances), not {a.dtype}")
+    if a.size and (int(a.min()) < np.iinfo(np.int32).min or int(a.max()) > np.iinfo(np.int32).max):
+        raise ValueError("dist values must fit int32")
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
 class Colony:
     """One Ant System instance resident on a GPU.
 
@@ -141,9 +156,7 @@ class Colony:
                  seed: int = 1, atomic: bool = True, device="cuda", stream=None):
         import torch
 
-        d = np.ascontiguousarray(dist, dtype=np.int32)
-        if d.ndim != 2 or d.shape[0] != d.shape[1]:
-            raise ValueError("dist must be a square matrix")
+        d = as_dist(dist)
         self.n, self.m = int(d.shape[0]), int(m)
         self.params = Params(self.n, self.m, alpha, beta, rho, seed)
         self.device = torch.device(device)
@@ -346,7 +359,7 @@ class Batch:
         import torch
 
         self.count = len(dists)
-        self._dists = [np.ascontiguousarray(d, dtype=np.int32) for d in dists]
+        self._dists = [as_dist(d) for d in dists]
         arr = (Params * self.count)()
         for q, (d, p) in enumerate(zip(self._dists, params)):
             arr[q] = Params(d.shape[0], p["m"], p.get("alpha", 1), p.get("beta", 2),

@@ -89,7 +89,7 @@ class Server:
         """Admits `req` if a slot and pool memory are free; None if refused."""
         p = Params(req.n, req.m, req.alpha, req.beta, req.rho, req.seed)
         slot = ctypes.c_int32(-1)
-        d = np.ascontiguousarray(req.dist, np.int32)
+        d = _aco.as_dist(req.dist)
         st = lib.aco_server_submit(self._s, ctypes.byref(p), d.ctypes.data_as(ctypes.c_void_p),
                                    req.iters, req.rid, ctypes.byref(slot))
         if st in (ACO_ERR_NOMEM, ACO_ERR_STATE):

@@ -250,3 +250,16 @@ def test_binding_loads_torch_hip_runtime():
     libs = ast.literal_eval(out.strip().splitlines()[-1])
     assert len(libs) == 1 and os.sep + "torch" + os.sep in libs[0], libs
 
+
+
+def test_distance_input_is_checked_not_cast(aco):
+    """Distances reach the library unchanged: integer input is converted to
+    int32 only when it fits, anything else is refused."""
+    ok = aco.as_dist(np.array([[0, 7], [7, 0]], np.int64))
+    assert ok.dtype == np.int32 and ok.flags["C_CONTIGUOUS"] and ok[0, 1] == 7
+    with pytest.raises(TypeError):
+        aco.as_dist(np.array([[0.0, 1.5], [1.5, 0.0]]))
+    with pytest.raises(ValueError):
+        aco.as_dist(np.array([[0, 2**40], [2**40, 0]], np.int64))
+    with pytest.raises(ValueError):
+        aco.as_dist(np.zeros((2, 3), np.int32))
