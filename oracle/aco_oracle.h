@@ -26,6 +26,14 @@
  *     to the evaporated binary32 value with one rounding;
  *   - tau0 = m / C_nn with C_nn the nearest-neighbour tour length from city 0;
  *   - Q = 1 (deposit 1/C^k), evaporation on all n^2 cells.
+ *
+ * Every function below is pinned by tests/test_oracle_pins.py against
+ * something other than itself: a third-party Philox engine (run, not
+ * copied), exact rational arithmetic, closed forms, brute force on tiny
+ * instances, invariants of the update, and chi-square tests of the sampled
+ * selection probabilities.  tests/test_oracle_mutants.py makes plausible
+ * mistakes in a copy of aco_oracle.c and checks that the pins catch each
+ * one.  No function here is "parity unpinned".
  */
 #ifndef ACO_ORACLE_H
 #define ACO_ORACLE_H
