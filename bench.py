@@ -507,7 +507,7 @@ def bench_batch(args, torch, aco):
         "roofline": job_roofline(
             float(sum(construct_bytes(int(n), int(n)) for n in sizes)) * iters, t_batch, count),
     }
-    aco.set_tile(1, 4096, 8)
+    aco.reset_tiles()
     print(json.dumps(rec), flush=True)
 
 

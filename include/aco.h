@@ -258,9 +258,13 @@ aco_status aco_test_product_select(int32_t n, int32_t count, const float* rows_d
  * paper's city tiling, Section III-A).  The tile changes speed only, never
  * results.  aco_set_tile sets the tile for instance sizes n_lo..n_hi (tile 4
  * only for n <= 1024); contexts and batches created afterwards use it.  The
- * table is process-wide and not thread-safe.  Default: 8 for every n. */
+ * table is process-wide and not thread-safe.  Default: 4 for n <= 256, 8
+ * above (the faster tile of each size for single-instance construction with
+ * m = n on MI355X). */
 aco_status aco_set_tile(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane);
 int32_t aco_get_tile(int32_t n);
+/* Restores the default table (above).  Same thread-safety as aco_set_tile. */
+void aco_reset_tiles(void);
 
 /* Autotuner: for each of the `count` strictly increasing instance sizes
  * (3..4096), builds a synthetic uniform instance with m = n on d_workspace

@@ -74,6 +74,7 @@ def _load():
         "aco_test_select": (i32, [i32, i32, i32, vp, vp, vp, vp, vp]),
         "aco_set_tile": (i32, [i32, i32, i32]),
         "aco_get_tile": (i32, [i32]),
+        "aco_reset_tiles": (None, []),
         "aco_autotune": (i32, [vp, sz, vp, i32, i32, vp, vp, vp, vp]),
         "aco_batch_workspace_bytes": (sz, [i32, vp]),
         "aco_batch_init": (i32, [c.POINTER(vp), i32, vp, vp, vp, sz, vp]),
@@ -321,6 +322,11 @@ def test_product_select(rows, feasible, u, stream=None):
 
 def set_tile(n_lo: int, n_hi: int, cities_per_lane: int):
     _check(lib.aco_set_tile(n_lo, n_hi, cities_per_lane), "aco_set_tile")
+
+
+def reset_tiles():
+    """Restores the library's default construction tiles (aco_reset_tiles)."""
+    lib.aco_reset_tiles()
 
 
 def get_tile(n: int) -> int:

@@ -37,6 +37,7 @@ hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t b
                            hipStream_t stream);
 int tile_for(int n);
 bool set_tile_range(int lo, int hi, int tile);
+void reset_tiles();
 
 }  // namespace host
 }  // namespace aco

@@ -130,17 +130,20 @@ def test_probe_and_select_validation(aco):
 
 
 def test_tile_table(aco):
-    assert aco.get_tile(2400) == 8
+    aco.reset_tiles()
+    # default: tile 4 up to n = 256, 8 above
+    assert [aco.get_tile(n) for n in (3, 256, 257, 2400, 4096)] == [4, 4, 8, 8, 8]
     with pytest.raises(aco.AcoError):
         aco.set_tile(900, 1100, 4)  # tile 4 stops at n = 1024
     with pytest.raises(aco.AcoError):
         aco.set_tile(10, 5, 8)
     with pytest.raises(aco.AcoError):
         aco.set_tile(10, 20, 5)
+    aco.set_tile(1, 4096, 8)
     aco.set_tile(100, 200, 4)
     assert [aco.get_tile(n) for n in (99, 100, 200, 201)] == [8, 4, 4, 8]
-    aco.set_tile(1, 4096, 8)
-    assert aco.get_tile(150) == 8
+    aco.reset_tiles()
+    assert [aco.get_tile(n) for n in (150, 300)] == [4, 8]
 
 
 def test_batch_workspace_and_validation(aco):

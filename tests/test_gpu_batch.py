@@ -26,7 +26,7 @@ def _cuda():
     from paper_1101_2678_amd import aco
 
     yield
-    aco.set_tile(1, 4096, 8)  # leave the default table for later tests
+    aco.reset_tiles()  # leave the default table for later tests
 
 
 @pytest.fixture
@@ -35,7 +35,7 @@ def tile4():
 
     aco.set_tile(1, 1024, 4)
     yield
-    aco.set_tile(1, 4096, 8)
+    aco.reset_tiles()
 
 
 @pytest.mark.parametrize("n", [1, 3, 63, 64, 65, 255, 256, 257, 700, 1024])
@@ -86,6 +86,7 @@ def test_batch_matches_single(graph, tiles):
     from paper_1101_2678_amd import aco
     from paper_1101_2678_amd.aco import Batch, Colony
 
+    aco.set_tile(1, 4096, 8)
     if tiles == "mixed":
         aco.set_tile(1, 300, 4)
     try:
@@ -109,7 +110,7 @@ def test_batch_matches_single(graph, tiles):
             c.close()
         b.close()
     finally:
-        aco.set_tile(1, 4096, 8)
+        aco.reset_tiles()
 
 
 @pytest.mark.parametrize("max_n", [1024, 1025, 2048, 2049, 3072, 3073, 4096])
@@ -143,7 +144,7 @@ def test_batch_pass_bounds(max_n):
             c.close()
         b.close()
     finally:
-        aco.set_tile(1, 4096, 8)
+        aco.reset_tiles()
 
 
 def test_batch256_full_size():
@@ -183,7 +184,7 @@ def test_batch256_full_size():
             assert b.best(q)[1] == st.best_len
         b.close()
     finally:
-        aco.set_tile(1, 4096, 8)
+        aco.reset_tiles()
 
 
 def test_batch_against_oracle():
@@ -241,4 +242,4 @@ def test_autotune_sets_table_and_keeps_results():
         _, d = tsp_inputs.instance(300, "uniform", side=1_000_000, seed=9)
         compare_run(d, 80, 1, 2, 0.5, 9, 2, kinds=("gather",))
     finally:
-        aco.set_tile(1, 4096, 8)
+        aco.reset_tiles()
