@@ -106,10 +106,13 @@ size_t aco_workspace_bytes(const aco_params* p, int32_t with_atomic);
  *                library; it holds tau, choice, distances, tours and all
  *                per-iteration state.  If ws_bytes also covers the atomic
  *                size, ACO_UPDATE_ATOMIC is available.
- *   hip_stream   the stream every later call of this context enqueues on
+ *   hip_stream   the stream every later call of this context enqueues on;
+ *                NULL (the default stream) or a stream created on the current
+ *                device by the HIP runtime this library is linked against
  * Uploads the distances, computes C_nn and tau0 on the GPU, fills tau and
- * choice.  Synchronous.  Errors: ACO_ERR_INVALID (parameters, distances),
- * ACO_ERR_NOMEM (workspace), ACO_ERR_DEVICE. */
+ * choice.  Synchronous.  Errors: ACO_ERR_INVALID (parameters, distances, a
+ * stream of another device), ACO_ERR_NOMEM (workspace), ACO_ERR_DEVICE (a
+ * stream handle the runtime does not know, or a failed HIP call). */
 aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host,
                     void* d_workspace, size_t ws_bytes, void* hip_stream);
 
@@ -291,7 +294,8 @@ size_t aco_batch_workspace_bytes(int32_t count, const aco_params* params);
  * state lives in d_workspace (caller-owned, 256-byte aligned, >=
  * aco_batch_workspace_bytes).  Instances are scheduled largest n first.
  * Every instance starts at iteration 0 and computes exactly what a context of
- * its own computes with the gather update.  Synchronous. */
+ * its own computes with the gather update.  hip_stream as for aco_init (same
+ * errors).  Synchronous. */
 aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* params,
                           const int32_t* const* dist_hosts, void* d_workspace, size_t ws_bytes,
                           void* hip_stream);
@@ -320,9 +324,13 @@ void aco_batch_destroy(aco_batch* b);
  * hardware byte counters and to measure achievable bandwidth.  Async. */
 aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
 
-/* Reads `bytes` (multiple of 16) of src_dev `reps` times and writes one
- * float per workgroup to sink_dev (>= 4096 floats): read bandwidth at a
- * footprint that fits or does not fit the on-die caches.  Async. */
+/* Reads `bytes` (multiple of 16) of src_dev `reps` times in all and writes
+ * one float per workgroup to sink_dev (>= 4096 floats, device): the
+ * streaming read bandwidth of a footprint.  Each of the eight XCDs walks the
+ * whole buffer in 16 KB chunks (reps / 8 times), so every XCD's L2 sees the
+ * full footprint, as it does in tour construction: a buffer larger than the
+ * L2 (4 MB per XCD) is served by the Infinity Cache (256 MB) or, beyond that,
+ * by HBM.  Algorithmic bytes: bytes * reps.  Asynchronous. */
 aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
                           void* hip_stream);
 

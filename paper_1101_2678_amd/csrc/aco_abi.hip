@@ -12,22 +12,12 @@
 #include <vector>
 
 #include "aco.h"
+#include "aco_ctx.hpp"
 #include "aco_host.hpp"
 #include "aco_state.hpp"
 #include "nn.hpp"
 #include "product.hpp"
 
-struct aco_ctx {
-    aco::Colony col;
-    aco::NnTables nn;       // candidate lists; nn.nn == 0 until aco_nn_attach
-    hipStream_t stream;
-    size_t ws_bytes;
-    uint32_t next_iter;     // first iteration aco_solve runs
-    uint32_t pending_iter;  // iteration of the construction awaiting update
-    bool pending;           // a construction has not been followed by an update
-    bool poisoned;
-    bool has_atomic;
-};
 
 namespace aco {
 namespace host {
@@ -45,6 +35,25 @@ aco_status device_fail(bool* poisoned, hipError_t e, const char* where) {
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// A stream handle must belong to the HIP runtime this library runs on and to
+// `device`.  Work enqueued on a handle the runtime does not know would not be
+// ordered with the library's other calls on that stream, so such a handle is
+// refused up front.  NULL (the default stream) is always accepted.
+aco_status stream_on_device(void* hip_stream, int device, const char* where) {
+    if (!hip_stream) return ACO_OK;
+    hipDevice_t owner = -1;
+    const hipError_t e = hipStreamGetDevice(static_cast<hipStream_t>(hip_stream), &owner);
+    if (e != hipSuccess)
+        return fail(ACO_ERR_DEVICE, std::string(where) +
+                                        ": the stream is not a stream of this HIP runtime (" +
+                                        hipGetErrorString(e) + ")");
+    if ((int)owner != device)
+        return fail(ACO_ERR_INVALID, std::string(where) + ": the stream belongs to device " +
+                                         std::to_string((int)owner) + ", not the current device " +
+                                         std::to_string(device));
+    return ACO_OK;
+}
 
 bool params_valid(const aco_params* p, std::string* why) {
     if (!p) return (*why = "params is NULL", false);
@@ -219,6 +228,34 @@ aco_status sync_ctx(aco_ctx* c, const char* where) {
 
 }  // namespace
 
+namespace aco {
+namespace host {
+
+aco_status update_ready(aco_ctx* c) {
+    if (aco_status s = usable(c)) return s;
+    if (!c->pending) return fail(ACO_ERR_STATE, "aco_update needs a preceding aco_construct");
+    return ACO_OK;
+}
+
+aco_status enqueue_update(aco_ctx* c, aco_update_kind kind, double* delta) {
+    // the update kernels also keep the best-so-far tour
+    hipError_t e;
+    if (kind == ACO_UPDATE_GATHER) {
+        e = launch_update_gather(c->col, c->stream);
+    } else {
+        Colony col = c->col;
+        if (delta) col.delta = delta;
+        e = launch_update_atomic(col, c->stream);
+    }
+    if (e != hipSuccess) return ::device_fail(c, e, "aco_update");
+    c->pending = false;
+    c->next_iter = c->pending_iter + 1;
+    return ACO_OK;
+}
+
+}  // namespace host
+}  // namespace aco
+
 extern "C" {
 
 const char* aco_status_str(aco_status s) {
@@ -256,8 +293,14 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     if (ws_bytes < L.base_end)
         return fail(ACO_ERR_NOMEM, "workspace smaller than aco_workspace_bytes(p, 0)");
 
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess)
+        return fail(ACO_ERR_DEVICE, "aco_init: no current HIP device");
+    if (aco_status s = aco::host::stream_on_device(hip_stream, device, "aco_init")) return s;
+
     aco_ctx* c = new (std::nothrow) aco_ctx();
     if (!c) return fail(ACO_ERR_NOMEM, "host allocation failed");
+    c->device = device;
     c->has_atomic = ws_bytes >= L.atomic_end;
     c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic,
                               aco::host::tile_for(p->n));
@@ -295,19 +338,12 @@ aco_status aco_construct(aco_ctx* c, uint32_t iter) {
 }
 
 aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
-    if (aco_status s = usable(c)) return s;
-    if (!c->pending) return fail(ACO_ERR_STATE, "aco_update needs a preceding aco_construct");
+    if (aco_status s = aco::host::update_ready(c)) return s;
     if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
         return fail(ACO_ERR_INVALID, "unknown update kind");
     if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
         return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
-    // the update kernels also keep the best-so-far tour
-    const hipError_t e = (kind == ACO_UPDATE_GATHER) ? aco::launch_update_gather(c->col, c->stream)
-                                                     : aco::launch_update_atomic(c->col, c->stream);
-    if (e != hipSuccess) return device_fail(c, e, "aco_update");
-    c->pending = false;
-    c->next_iter = c->pending_iter + 1;
-    return ACO_OK;
+    return aco::host::enqueue_update(c, kind, nullptr);
 }
 
 static aco_status solve_with(aco_ctx* c, uint32_t iters, aco_update_kind kind,

@@ -27,6 +27,9 @@ aco_status fail(aco_status s, const std::string& why);
 // Records a device failure (poisoning the owner if `poisoned` is given).
 aco_status device_fail(bool* poisoned, hipError_t e, const char* where);
 size_t round_up(size_t v, size_t a);
+// ACO_OK if hip_stream (NULL: the default stream) is a stream of this HIP
+// runtime on `device`; otherwise the failure is recorded under `where`.
+aco_status stream_on_device(void* hip_stream, int device, const char* where);
 bool params_valid(const aco_params* p, std::string* why);
 bool dist_valid(const int32_t* d, int n, int m, std::string* why);
 Layout make_layout(const aco_params& p);

@@ -172,6 +172,10 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
     if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
         return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
     if (ws_bytes < B.end) return fail(ACO_ERR_NOMEM, "workspace smaller than aco_batch_workspace_bytes");
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess)
+        return fail(ACO_ERR_DEVICE, "aco_batch_init: no current HIP device");
+    if (aco_status s = aco::host::stream_on_device(hip_stream, device, "aco_batch_init")) return s;
 
     aco_batch* b = new (std::nothrow) aco_batch();
     if (!b) return fail(ACO_ERR_NOMEM, "host allocation failed");

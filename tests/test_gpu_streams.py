@@ -60,3 +60,47 @@ def test_batch_workspace_outlives_queued_work():
     x.fill_(9)
     torch.cuda.synchronize()
     assert bool((x == 9).all()), "a dropped batch's workspace was reused while its kernels ran"
+
+
+def test_init_refuses_unknown_stream_handle():
+    """A stream handle the library's HIP runtime does not know is refused by
+    aco_init (and by aco_batch_init) before anything is enqueued: work on it
+    would not be ordered with the context's later reads.  The handle used is
+    the address of ordinary host memory, never a stream."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_1101_2678_amd import aco
+
+    _, d = tsp_inputs.instance(50, "uniform", side=10_000, seed=1)
+    d = aco.as_dist(d)
+    p = aco.Params(50, 50, 1, 2, 0.5, 1)
+    nbytes = aco.lib.aco_workspace_bytes(ctypes.byref(p), 0)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    bogus = (ctypes.c_uint8 * 4096)()          # valid host memory, not a stream
+    ctx = ctypes.c_void_p()
+    st = aco.lib.aco_init(ctypes.byref(ctx), ctypes.byref(p), d.ctypes.data_as(ctypes.c_void_p),
+                          ctypes.c_void_p(ws.data_ptr()), nbytes,
+                          ctypes.c_void_p(ctypes.addressof(bogus)))
+    assert st == aco.ACO_ERR_DEVICE, st
+    assert not ctx.value
+    assert b"not a stream of this HIP runtime" in aco.lib.aco_last_error()
+    # torch's own streams (default and side) are accepted
+    for s in (torch.cuda.current_stream(), torch.cuda.Stream()):
+        col = aco.Colony(d, 50, 1, 2, 0.5, 1, atomic=False, stream=s)
+        col.construct(0)
+        col.update("gather")
+        col.sync()
+        col.close()
+    ptrs = (ctypes.c_void_p * 1)(d.ctypes.data)
+    b = ctypes.c_void_p()
+    bb = aco.lib.aco_batch_workspace_bytes(1, ctypes.byref(p))
+    bws = torch.empty(bb, dtype=torch.uint8, device="cuda")
+    st = aco.lib.aco_batch_init(ctypes.byref(b), 1, ctypes.byref(p), ptrs,
+                                ctypes.c_void_p(bws.data_ptr()), bb,
+                                ctypes.c_void_p(ctypes.addressof(bogus)))
+    assert st == aco.ACO_ERR_DEVICE and not b.value
+    torch.cuda.synchronize()
+    assert np.frombuffer(bogus, np.uint8).sum() == 0   # the host memory was never written
