@@ -13,21 +13,40 @@ __global__ __launch_bounds__(256) void k_probe_copy(float4* __restrict__ dst,
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
 }
 
-// Each workgroup streams its share of the buffer `reps` times; the sum keeps
-// the loads alive and goes to sink[blockIdx.x].
-__global__ __launch_bounds__(256) void k_probe_read(const float4* __restrict__ src, size_t n16,
-                                                    int reps, float* sink) {
-    const size_t stride = (size_t)gridDim.x * 256;
+// Streaming read of a buffer `reps` times.  The buffer is cut into 16 KB
+// chunks (256 threads x 4 loads of 16 bytes, all four in flight before any
+// is used).  Workgroups go to the eight XCDs round-robin by index, so work
+// item w runs on XCD w mod 8; XCD x walks the whole buffer chunk by chunk,
+// starting x/8 of the way in.  Every XCD's L2 therefore sees the whole
+// footprint cycling through it, as in tour construction, where every XCD
+// reads rows from the whole choice matrix: a footprint above the L2 is
+// served from the Infinity Cache (MALL) or HBM, one below it from the L2.
+// The sum keeps the loads alive and goes to sink[blockIdx.x].
+constexpr int kStreamThreads = 256;
+constexpr int kStreamLoads = 4;
+constexpr size_t kStreamChunk16 = (size_t)kStreamThreads * kStreamLoads;  // 16-byte units
+
+__global__ __launch_bounds__(kStreamThreads) void k_probe_read(const float4* __restrict__ src,
+                                                               size_t n16, size_t chunks,
+                                                               size_t items, float* sink) {
     float acc = 0.0f;
-    for (int r = 0; r < reps; ++r)
-        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
-            const float4 v = src[i];
-            acc += (v.x + v.y) + (v.z + v.w);
+    for (size_t w = blockIdx.x; w < items; w += gridDim.x) {
+        const size_t x = w & 7, k = w >> 3;
+        const size_t c = (k + x * (chunks / 8 + 1)) % chunks;
+        const size_t base = c * kStreamChunk16 + threadIdx.x;
+        float4 v[kStreamLoads];
+#pragma unroll
+        for (int u = 0; u < kStreamLoads; ++u) {
+            const size_t i = base + (size_t)u * kStreamThreads;
+            v[u] = i < n16 ? src[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
-    __shared__ float red[256];
+#pragma unroll
+        for (int u = 0; u < kStreamLoads; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    __shared__ float red[kStreamThreads];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = kStreamThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -112,8 +131,14 @@ hipError_t launch_probe_read(const void* src, size_t bytes, int reps, float* sin
                              hipStream_t s) {
     const size_t n16 = bytes / 16;
     if (n16 == 0 || reps <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_probe_read, dim3(kProbeBlocks), dim3(256), 0, s,
-                       reinterpret_cast<const float4*>(src), n16, reps, sink);
+    // chunks * reps work items in all, so each XCD walks the whole buffer
+    // reps / 8 times; the grid is a multiple of 8 workgroups (or one work item
+    // per workgroup), so work item w always runs on XCD w mod 8.
+    const size_t chunks = (n16 + kStreamChunk16 - 1) / kStreamChunk16;
+    const size_t items = chunks * (size_t)reps;
+    const int blocks = (int)(items < (size_t)kProbeBlocks ? items : (size_t)kProbeBlocks);
+    hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(kStreamThreads), 0, s,
+                       reinterpret_cast<const float4*>(src), n16, chunks, items, sink);
     return hipGetLastError();
 }
 
