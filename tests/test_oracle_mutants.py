@@ -63,6 +63,15 @@ MUTANTS = {
     "s64_row2_carry": (
         "else if (row == 2) out[t] = a[t] + x;", "else if (row == 2) out[t] = a[t] + r1;",
         [("test_s64_integers_exact", None), ("test_s64_total_is_pairwise_tree", None)]),
+    "s64_row2_association": (
+        "else if (row == 2) out[t] = a[t] + x;", "else if (row == 2) out[t] = (a[t] + r1) + r0;",
+        [("test_s64_association_hand_values", None)]),
+    "s64_row3_association": (
+        "else out[t] = (a[t] + r2) + x;", "else out[t] = a[t] + (r2 + x);",
+        [("test_s64_association_hand_values", None)]),
+    "s64_row3_carry_order": (
+        "else out[t] = (a[t] + r2) + x;", "else out[t] = (a[t] + x) + r2;",
+        [("test_s64_association_hand_values", None)]),
     "s64_stage_a_crosses_rows": (
         "float left = (pos >= shift) ? a[t - shift] : 0.0f;",
         "float left = (t >= shift) ? a[t - shift] : 0.0f;",

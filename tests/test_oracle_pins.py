@@ -262,6 +262,16 @@ def test_s64_integers_exact(oracle_lib):
         assert [Fraction(float(v)) for v in oracle_lib.s64(x)] == list(ex)
 
 
+def test_s64_association_hand_values(oracle_lib):
+    """Which partial sums the tree adds in which order, pinned by a hand-derived
+    example whose roundings tell the associations apart (the derivation is in
+    the fixture's citation): entries 16..63 take the stage-B carries exactly as
+    the tree defines them."""
+    g = GOLD["s64_association"]
+    out = oracle_lib.s64(np.array(g["input"], np.float32))
+    assert [f32bits(v) for v in out] == [f32bits(v) for v in g["output"]]
+
+
 def test_s64_total_is_pairwise_tree(oracle_lib):
     """Entry 63 of the tree is a balanced pairwise sum: ((x0+x1)+(x2+x3))+..."""
     rng = np.random.default_rng(11)
