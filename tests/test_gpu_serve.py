@@ -51,6 +51,36 @@ def test_served_results_equal_alone():
     srv.close()
 
 
+def test_served_results_match_oracle():
+    """Requests served in a mix against the oracle directly (not only against
+    the library's own standalone path): small instances with uneven iteration
+    counts, both layouts, and two above 1000 cities, all running at once; each
+    best tour, best length and final tau bit-exact against oracle.solve with
+    the request's parameters and seed (Section II, Eqs. 1-4)."""
+    import oracle
+    from gpu_helpers import ORACLE_THREADS
+    from paper_1101_2678_amd.serve import Request, Server, run_open_loop
+
+    specs = [(17, "uniform", 6), (64, "cluster", 3), (150, "uniform", 9), (333, "cluster", 5),
+             (700, "uniform", 4), (1100, "cluster", 3), (1500, "uniform", 2)]
+    reqs = []
+    for q, (n, layout, iters) in enumerate(specs):
+        _, d = tsp_inputs.instance(n, layout, side=1_000_000, seed=300 + q)
+        reqs.append(Request(rid=q, arrival=0.0, dist=d, m=n, iters=iters, seed=77 + 13 * q,
+                            layout=layout))
+    srv = Server(pool_bytes=1 << 30, max_slots=8)
+    summary = run_open_loop(srv, reqs, keep_tau=True)
+    srv.close()
+    log(f"  served vs oracle: {summary}")
+    assert summary["peak_running"] >= 4
+    for r in reqs:
+        st = oracle.solve(r.dist, r.m, r.alpha, r.beta, r.rho, r.seed, r.iters,
+                          threads=ORACLE_THREADS)
+        assert r.best_len == st.best_len, f"request {r.rid} (n={r.n}): {r.best_len} != {st.best_len}"
+        assert (r.best_tour == st.best_tour).all(), f"request {r.rid}: best tour differs"
+        assert_same_f32(r.extra["tau"], st.tau, f"request {r.rid} (n={r.n}) tau")
+
+
 def test_served_trace_at_benchmark_sizes():
     """The first 30 requests of the benchmark's trace (Poisson 200/s, n
     log-uniform in [100, 3000], both layouts, 50 iterations each, per-request
