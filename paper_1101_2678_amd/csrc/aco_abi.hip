@@ -44,10 +44,15 @@ aco_status stream_on_device(void* hip_stream, int device, const char* where) {
     if (!hip_stream) return ACO_OK;
     hipDevice_t owner = -1;
     const hipError_t e = hipStreamGetDevice(static_cast<hipStream_t>(hip_stream), &owner);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        // The runtime also keeps the failure as this thread's last error; the
+        // launch checks (hipGetLastError after each launch) of the next call
+        // would report it as their own, so it is consumed here.
+        (void)hipGetLastError();
         return fail(ACO_ERR_DEVICE, std::string(where) +
                                         ": the stream is not a stream of this HIP runtime (" +
                                         hipGetErrorString(e) + ")");
+    }
     if ((int)owner != device)
         return fail(ACO_ERR_INVALID, std::string(where) + ": the stream belongs to device " +
                                          std::to_string((int)owner) + ", not the current device " +
