@@ -129,6 +129,24 @@ aco_status aco_construct(aco_ctx* c, uint32_t iter);
  * atomic workspace. */
 aco_status aco_update(aco_ctx* c, aco_update_kind kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * aco_update(c, ACO_UPDATE_ATOMIC) with the binary64 deposit matrix held in
+ * a static device array of the library (8 MiB per GPU, kept until the
+ * process ends) instead of the workspace, so the context may have been
+ * created with aco_workspace_bytes(p, 0).  Same results, bit for bit, as
+ * aco_update(c, ACO_UPDATE_ATOMIC).  Allocates nothing: no hipMalloc, no
+ * hipFree, no allocating library call.
+ *   Limit: n <= 1024 (n * ld <= 2^20 cells), else ACO_ERR_INVALID and nothing
+ *   is enqueued.
+ *   The array is cleared on the context's stream at the start of every call.
+ *   Every call on one GPU shares it: calls whose work overlaps on one GPU
+ *   (contexts on different streams, not ordered by the caller) race and give
+ *   wrong tau.
+ * Asynchronous.  Other errors as aco_update; ACO_ERR_DEVICE if the array's
+ * device address could not be obtained at aco_init. */
+aco_status aco_update_atomic_noalloc(aco_ctx* c);
+
 /* Runs `iters` iterations (construct, update) starting at the context's
  * iteration counter, then copies the best-so-far tour (n+1 uint16, host) and
  * its length (host) out.  Synchronous.  Either output pointer may be NULL. */

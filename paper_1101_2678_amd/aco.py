@@ -51,6 +51,7 @@ def _load():
         "aco_init": (i32, [c.POINTER(vp), c.POINTER(Params), vp, vp, sz, vp]),
         "aco_construct": (i32, [vp, u32]),
         "aco_update": (i32, [vp, i32]),
+        "aco_update_atomic_noalloc": (i32, [vp]),
         "aco_solve": (i32, [vp, u32, i32, vp, vp]),
         "aco_read_tours": (i32, [vp, vp, vp]),
         "aco_construct_product": (i32, [vp, u32]),
@@ -209,6 +210,11 @@ class Colony:
 
     def update(self, kind="gather"):
         _check(lib.aco_update(self._ctx, _KIND[kind]), "aco_update")
+
+    def update_atomic_noalloc(self):
+        """The atomic update with the library's static deposit matrix
+        (aco_update_atomic_noalloc: n <= 1024, no workspace part needed)."""
+        _check(lib.aco_update_atomic_noalloc(self._ctx), "aco_update_atomic_noalloc")
 
     # ---- synchronous calls
     def solve(self, iters: int, kind="gather", rule: str = "r64"):

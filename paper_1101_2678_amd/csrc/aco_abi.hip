@@ -306,6 +306,7 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     aco_ctx* c = new (std::nothrow) aco_ctx();
     if (!c) return fail(ACO_ERR_NOMEM, "host allocation failed");
     c->device = device;
+    c->scratch_err = aco::host::noalloc_scratch(device, &c->scratch);
     c->has_atomic = ws_bytes >= L.atomic_end;
     c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic,
                               aco::host::tile_for(p->n));

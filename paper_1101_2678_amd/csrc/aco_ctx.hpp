@@ -19,6 +19,8 @@ struct aco_ctx {
     bool pending;           // a construction has not been followed by an update
     bool poisoned;
     bool has_atomic;
+    void* scratch;          // this device's address of the static deposit matrix, or null
+    hipError_t scratch_err; // why it is null
 };
 
 namespace aco {
@@ -31,6 +33,10 @@ aco_status enqueue_update(aco_ctx* c, aco_update_kind kind, double* delta);
 // ACO_OK if the context can take an update now (not poisoned, a
 // construction pending), else the status aco_update would return.
 aco_status update_ready(aco_ctx* c);
+// Device address of the static deposit matrix of aco_update_atomic_noalloc
+// on `device`, which must be current; looked up on the first call for each
+// device and remembered.  *out is null if the lookup failed.
+hipError_t noalloc_scratch(int device, void** out);
 
 }  // namespace host
 }  // namespace aco

@@ -36,6 +36,9 @@ struct Colony {
 
 constexpr int kMaxCities = 4096;
 constexpr int kMaxTile4Cities = 1024;  // tile 4 holds 16 passes of 256 cities at most
+// Largest n aco_update_atomic_noalloc takes (its static deposit matrix holds
+// n * ld binary64 cells, ld = n rounded up to 64).
+constexpr int kMaxNoallocCities = 1024;
 
 // Whether the construction kernel has a variant with `tile` cities per lane
 // for n cities.
