@@ -3,26 +3,30 @@
 
 A step is one AS iteration over the resident instance: tour construction by
 all m ants (Section II, Eq. 1), then the best-so-far tour and the pheromone
-update (Eqs. 2-4, gather variant) with the choice refresh.  The default
+update (Eqs. 2-4, gather variant) with the choice refresh.  The headline
 workload is n = m = 2400 cities uniform in [0, 10^6]^2 (the largest size the
 paper measures), alpha = 1, beta = 2, rho = 0.5, Philox seed 1; the instance
 and all state are resident in HBM before timing starts.
 
 Prints one JSON line.  `value` is ant-steps per second of the whole step
-(m (n-1) roulette selections per step).  Extra fields: per-kernel times from
-HIP events on the launch stream, update GB/s for both variants, the roofline
-of the construction kernel (with the counter traffic when it was taken on the
-current kernel source), live bandwidth probes, the same steps with
-candidate-list construction (`nn_list`) and with the product-and-argmax rule
-(`product`, with its own ALU roofline), and the oracle timed on a bounded
-sample on the host (`cpu_baseline`).
+(m (n-1) roulette selections per step).  The construction roofline is taken
+against the streaming read bandwidth measured live at the choice matrix's
+own footprint (the Infinity Cache at n = 2400), with the published HBM peak
+beside it; each update kernel is set against one copy launch over its own
+footprint.  Further fields: per-kernel times from HIP events on the launch
+stream, the counter traffic when it was taken on the current kernel source,
+HBM and 160 MB streaming probes, the same steps with candidate-list
+construction (`nn_list`) and with the product-and-argmax rule (`product`),
+the oracle timed on a bounded sample on the host (`cpu_baseline`), and under
+`configs` every other workload: n = 100, n = 1000 (uniform and 20-cluster),
+256 uneven instances as one graph-replayed batch against one instance per
+launch (`batch256`, solves/s), and a Poisson trace through the
+continuous-batching server against one request at a time (`served`, solves/s
+with p50 and p99).
 
-Other workloads: `--workload n1000u|n1000c|n100` (the same line at those
-sizes), `--workload batch256` (256 uneven instances as one graph-replayed
-batch against one instance per launch; solves/s) and `--workload served` (a
-Poisson trace through the continuous-batching server against one request at
-a time; solves/s with p50 and p99).  Profiled runs add `--sync-launches`.
-The library runs on one GPU: `--gpus` other than 1 exits with a message.
+`--workload NAME` runs one of them alone.  Profiled runs add
+`--sync-launches`.  The library runs on one GPU: `--gpus` other than 1 exits
+with a message.
 """
 from __future__ import annotations
 
@@ -93,11 +97,23 @@ def gather_bytes(n: int, m: int) -> int:
 
 
 def atomic_bytes(n: int, m: int) -> int:
-    """tours (2 m (n+1)) and deposits (4 m) read, m n binary64 atomics into
-    the upper triangle (8 B read + 8 B write each); epilogue: tau r/w, dist r,
-    choice w (16 n^2) and the upper-triangle deposits read and cleared
-    (8 n^2)."""
+    """Direct atomic update: tours (2 m (n+1)) and deposits (4 m) read, m n
+    binary64 atomics into the upper triangle (8 B read + 8 B write each);
+    epilogue: tau r/w, dist r, choice w (16 n^2) and the upper-triangle
+    deposits read and cleared (8 n^2)."""
     return 2 * m * (n + 1) + 4 * m + m * n * 16 + 24 * n * n
+
+
+def atomic_shared_bytes(n: int, m: int) -> int:
+    """Atomic update with the deposits combined in shared memory: the
+    successor table (2 m n) and the deposits (4 m) read, then the epilogue of
+    the direct variant (24 n^2).  The global atomics, one per distinct edge
+    of a row's workgroup, depend on the tours and are not counted."""
+    return 2 * m * n + 4 * m + 24 * n * n
+
+
+UPDATE_BYTES = {"gather": gather_bytes, "atomic": atomic_shared_bytes,
+                "atomic_direct": atomic_bytes}
 
 
 def traffic_from_profile():
@@ -193,47 +209,107 @@ def host_cpu_model() -> str:
     return f"{names[0]} ({len(names)} logical CPUs)" if names else "unknown"
 
 
-def probe_bandwidth(torch, aco, n: int, m: int):
-    """Live read bandwidth for the construction access pattern: `m` one-wave
-    workgroups each read n-1 random whole rows of n floats (aco_probe_rows),
-    from a matrix of the construction's own size (n x ld) and from larger ones
-    (160 MB: beyond L2, inside the 256 MB Infinity Cache; 1.3 GB: HBM).  Also
-    one plain 256 MiB copy (aco_probe_copy) that calibrates the hardware byte
-    counters in profiled runs."""
-    out = {}
-    ld = (n + 63) // 64 * 64
-    sink = torch.zeros(max(m, 4096), dtype=torch.float32, device="cuda")
-    for label, rows in [("same_footprint", n), ("160MB", (160 << 20) // (4 * ld)),
-                        ("1300MB", (1300 << 20) // (4 * ld))]:
-        mat = torch.rand(rows * ld, dtype=torch.float32, device="cuda")
-        aco.probe_rows(mat, rows, ld, n, m, 8, sink)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        aco.probe_rows(mat, rows, ld, n, m, n - 1, sink)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        out[f"random_rows_{label}_GBps"] = 4.0 * n * m * (n - 1) / (ms * 1e-3) / 1e9
-        out[f"random_rows_{label}_MB"] = rows * ld * 4 / 1e6
-        del mat
-    buf = torch.ones((2 << 30) // 4, dtype=torch.float32, device="cuda")
-    aco.probe_read(buf, 1, sink)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    aco.probe_read(buf, 3, sink)
-    e1.record()
-    torch.cuda.synchronize()
-    out["stream_read_2GiB_GBps"] = buf.numel() * 4 * 3 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+PROBE_SHAPES = ((4, False), (16, False), (8, True))  # (loads in flight, nontemporal)
+
+
+def stream_read_ceiling(torch, aco, nbytes: int, min_ms: float = 5.0) -> dict:
+    """Streaming read bandwidth of a buffer of `nbytes` (aco_probe_read_shape:
+    each of the eight XCDs walks the whole buffer, so every XCD's L2 sees the
+    full footprint, as in tour construction), the best over PROBE_SHAPES,
+    each timed with HIP events on the launch stream over at least `min_ms`.
+    A footprint above the 4 MB L2 of an XCD and within the 256 MB Infinity
+    Cache measures the Infinity Cache (MALL); one well above 256 MB measures
+    HBM."""
+    stream = torch.cuda.current_stream()
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(4096, dtype=torch.float32, device="cuda")
+    best, shapes = None, {}
+    for loads, nt in PROBE_SHAPES:
+        aco.probe_read(buf, 8, sink, loads=loads, nontemporal=nt)  # every XCD touches it once
+        reps, ms = 8, 0.0
+        for _ in range(12):
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            aco.probe_read(buf, reps, sink, loads=loads, nontemporal=nt)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            if ms >= min_ms:
+                break
+            reps = int(reps * min(64.0, max(2.0, 1.3 * min_ms / max(ms, 1e-3))) + 7) // 8 * 8
+        rate = nbytes * reps / (ms * 1e-3) / 1e9
+        shapes[f"{loads}{'nt' if nt else ''}"] = round(rate, 1)
+        if best is None or rate > best["GBps"]:
+            best = {"GBps": round(rate, 1), "bytes": int(nbytes), "reps": reps, "ms": round(ms, 3),
+                    "loads_in_flight": loads, "nontemporal": nt}
     del buf
-    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    best["by_shape_GBps"] = shapes
+    return best
+
+
+def copy_ceiling(torch, aco, nbytes: int, launches: int = 20) -> dict:
+    """Read-plus-write bandwidth of one aco_probe_copy launch over a footprint
+    of `nbytes` (half source, half destination), the mean of `launches`
+    single launches each timed with HIP events: the same footprint and the
+    same launch granularity as one update kernel."""
+    stream = torch.cuda.current_stream()
+    half = (nbytes // 2) // 16 * 16
+    src = torch.ones(half // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     aco.probe_copy(dst, src)
-    torch.cuda.synchronize()
-    out["copy_calibration_bytes"] = src.numel() * 4
+    times = []
+    for _ in range(launches):
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        aco.probe_copy(dst, src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
     del src, dst
-    return {k: (round(v, 1) if isinstance(v, float) else v) for k, v in out.items()}
+    ms = float(np.mean(times))
+    return {"GBps": round(2 * half / (ms * 1e-3) / 1e9, 1), "bytes": 2 * half,
+            "ms_per_launch": round(ms, 4)}
+
+
+def random_rows_rate(torch, aco, n: int, m: int, rows: int) -> float:
+    """GB/s of aco_probe_rows: m one-wave workgroups each read n - 1 random
+    whole rows of n floats from a rows x ld matrix (the construction's access
+    pattern without its arithmetic)."""
+    stream = torch.cuda.current_stream()
+    ld = (n + 63) // 64 * 64
+    sink = torch.zeros(max(m, 4096), dtype=torch.float32, device="cuda")
+    mat = torch.rand(rows * ld, dtype=torch.float32, device="cuda")
+    aco.probe_rows(mat, rows, ld, n, m, 8, sink)
+    e0, e1 = _events(torch)
+    e0.record(stream)
+    aco.probe_rows(mat, rows, ld, n, m, n - 1, sink)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    del mat
+    return round(4.0 * n * m * (n - 1) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+
+
+def requested_bytes(tours: np.ndarray, n: int, skip: bool) -> int:
+    """Bytes the construction kernel asks the memory system for in one launch
+    (16-byte loads of 4-city groups).  With the skip path a group is loaded
+    at step s only if one of its cities is still unvisited, i.e. at steps
+    1 .. (last position of the group's cities in the tour); without it every
+    group of the row is loaded at all n - 1 steps."""
+    groups = (n + 3) // 4
+    m = tours.shape[0]
+    if not skip:
+        return 16 * groups * (n - 1) * m
+    total = 0
+    for k0 in range(0, m, 256):
+        t = tours[k0:k0 + 256, :n].astype(np.int64)
+        pos = np.full((t.shape[0], groups * 4), -1, np.int64)
+        np.put_along_axis(pos, t, np.arange(n, dtype=np.int64)[None, :], axis=1)
+        total += int(pos.reshape(t.shape[0], groups, 4).max(axis=2).sum())
+    return 16 * total
 
 
 SYNC_LAUNCHES = False
@@ -286,7 +362,7 @@ def bench_nn(torch, aco, d, m: int, nn: int, steps: int, warmup: int, update: st
     `steps` iterations timed like the main loop, HIP events around each
     construction (candidate-table refresh included)."""
     n = d.shape[0]
-    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update == "atomic"))
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update != "gather"))
     col.attach_nn(nn)
     nnl = col.nn_lists()
     problem = nn_lists_problem(d, nnl)
@@ -379,7 +455,7 @@ def bench_product(torch, aco, d, m: int, steps: int, warmup: int, update: str, c
     `steps` iterations timed like the main loop, HIP events around each
     construction."""
     n = d.shape[0]
-    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update == "atomic"))
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=(update != "gather"))
     stream = torch.cuda.current_stream()
     it = 0
     for _ in range(warmup):
@@ -460,7 +536,14 @@ def bench_batch(args, torch, aco):
         f"tile8 {ms8.tolist()})")
     stream = torch.cuda.Stream()
     b = aco.Batch(dists, params, stream=stream)
-    b.run(iters, graph=True)  # captures the graph and runs iterations 0..24
+    default_cfg = b.config
+    # the batched launch's own autotuner: workgroups per CU x tile policy,
+    # timed on this batch (each candidate advances it by 3 iterations)
+    cands = [(w, t) for t in (-1, 0, 1024) for w in (0, 8, 12, 16, 20, 24, 32)]
+    best, cand_ms = b.autotune(cands, iters=2)
+    log(f"bench batch: launch autotune chose {cands[best]} ({cand_ms[best]:.3f} ms/iteration; "
+        f"default {default_cfg})")
+    b.run(iters, graph=True)  # captures the graph and runs 25 iterations
     b.sync()
     t0 = time.perf_counter()
     b.run(iters, graph=True)  # replays it: iterations 25..49
@@ -504,11 +587,19 @@ def bench_batch(args, torch, aco):
         "speedup_vs_one_per_launch": round(t_single / t_batch, 2),
         "ant_steps_per_s": round(ant_steps / t_batch, 1),
         "tiles": {"sizes": [64, 128, 256, 512, 1024], "chosen": chosen.tolist()},
+        "launch_autotune": {
+            "candidates": [{"wg_per_cu": w, "tile4_max_n": t, "ms_per_iteration": round(float(x), 4)}
+                           for (w, t), x in zip(cands, cand_ms)],
+            "chosen": {"wg_per_cu": cands[best][0], "tile4_max_n": cands[best][1]},
+            "default": default_cfg,
+            "note": "wg_per_cu: construction workgroups per CU allowed by the LDS request (0 = "
+                    "no cap); tile4_max_n: instances up to this n use 4 cities per lane (-1 = "
+                    "the tile table above, 0 = all 8)"},
         "roofline": job_roofline(
             float(sum(construct_bytes(int(n), int(n)) for n in sizes)) * iters, t_batch, count),
     }
     aco.reset_tiles()
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
 def bench_served(args, torch, aco):
@@ -527,14 +618,22 @@ def bench_served(args, torch, aco):
     pool = min(int(free * 0.5), 64 << 30)
     footprint = [r.footprint_bytes() for r in reqs]
     formula = [12 * r.n * r.n + 2 * r.m * r.n for r in reqs]
-    srv = serve.Server(pool_bytes=pool, max_slots=args.slots)
+    fifo_reqs = copy.deepcopy(reqs)
     log(f"bench served: {len(reqs)} requests, pool {pool / 1e9:.1f} GB, slots {args.slots}")
-    batched = serve.run_open_loop(srv, reqs)
+    srv = serve.Server(pool_bytes=pool, max_slots=args.slots)
+    batched = serve.run_open_loop(srv, reqs, policy="size")
     srv.close()
-    log(f"bench served: batched {batched}")
+    log(f"bench served: batched, size-aware admission {batched}")
+    srv = serve.Server(pool_bytes=pool, max_slots=args.slots)
+    fifo = serve.run_open_loop(srv, fifo_reqs, policy="fifo")
+    srv.close()
+    log(f"bench served: batched, FIFO admission {fifo}")
     plain = serve.run_plain(plain_reqs)
     log(f"bench served: plain {plain}")
-    mismatched = sum(int(a.best_len != b.best_len) for a, b in zip(reqs, plain_reqs))
+    mismatched = sum(int(a.best_len != b.best_len or not np.array_equal(a.best_tour, b.best_tour))
+                     for a, b in zip(reqs, plain_reqs))
+    mismatched += sum(int(a.best_len != b.best_len or not np.array_equal(a.best_tour, b.best_tour))
+                      for a, b in zip(fifo_reqs, plain_reqs))
     rec = {
         "metric": "served solves/s and p99 latency (50 AS iterations per request)",
         "value": round(batched["solves_per_s"], 3),
@@ -555,7 +654,10 @@ def bench_served(args, torch, aco):
                    "pool_bytes": pool},
         "latency_p50_s": round(batched["latency_p50_s"], 4),
         "latency_p99_s": round(batched["latency_p99_s"], 4),
+        "admission": "size-aware: requests waiting under 10 s offered smallest solve first, "
+                     "older ones first in arrival order",
         "batched": batched,
+        "batched_fifo_admission": fifo,
         "plain_one_request_at_a_time": plain,
         "results_differing_from_plain": mismatched,
         "footprint_bytes_total": int(sum(footprint)),
@@ -564,7 +666,149 @@ def bench_served(args, torch, aco):
         "roofline": job_roofline(float(sum(construct_bytes(r.n, r.m) * r.iters for r in reqs)),
                                  batched["makespan_s"], len(reqs)),
     }
-    print(json.dumps(rec), flush=True)
+    return rec
+
+
+def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool) -> dict:
+    """One resident instance of WORKLOADS[name]: `warmup` untimed iterations,
+    then `steps` timed iterations (construction, then the update of
+    args.update), HIP events around every construction and update on the
+    launch stream; then the other update variant on the same state.  The
+    construction roofline is taken against the streaming read ceiling
+    measured at the choice matrix's own footprint."""
+    wl = WORKLOADS[name]
+    n, m = wl["n"], wl["m"]
+    _, d = tsp_inputs.instance(n, wl["layout"], side=wl["side"], seed=wl["seed"])
+    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=True)
+    stream = torch.cuda.current_stream()
+    log(f"bench: {name} n={n} m={m} {col.describe()}")
+
+    it = 0
+    for _ in range(warmup):
+        col.construct(it)
+        launched(torch)
+        col.update(args.update)
+        launched(torch)
+        it += 1
+    torch.cuda.synchronize()
+
+    K = steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        ev[3 * s].record(stream)
+        col.construct(it)
+        launched(torch)
+        ev[3 * s + 1].record(stream)
+        col.update(args.update)
+        launched(torch)
+        ev[3 * s + 2].record(stream)
+        it += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_con = np.array([ev[3 * s].elapsed_time(ev[3 * s + 1]) for s in range(K)])
+    t_upd = np.array([ev[3 * s + 1].elapsed_time(ev[3 * s + 2]) for s in range(K)])
+    log(f"bench: {name}: timed {K} steps in {wall:.3f} s")
+    tours, _ = col.tours()
+    tile = int(col.describe().split("cities_per_lane=")[1].split()[0])
+
+    # the other update variants, timed after the timed region on the same state
+    t_other = {}
+    for kind in ("gather", "atomic", "atomic_direct"):
+        if kind == args.update:
+            continue
+        t_other[kind] = []
+        for _ in range(max(3, min(K, 10))):
+            col.construct(it)
+            launched(torch)
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            col.update(kind)
+            launched(torch)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_other[kind].append(e0.elapsed_time(e1))
+            it += 1
+    t_upd_v = {args.update: float(t_upd.mean())}
+    t_upd_v.update({k: float(np.mean(v)) for k, v in t_other.items()})
+    best_tour, best_len = col.best()
+    col.close()
+
+    ld = (n + 63) // 64 * 64
+    ant_steps = m * (n - 1)
+    ms_step = wall * 1e3 / K
+    con_ms = float(t_con.mean())
+    alg = construct_bytes(n, m)
+    achieved = alg / (con_ms * 1e-3) / 1e9
+    passes = (n + 64 * tile - 1) // (64 * tile)
+    req = requested_bytes(tours, n, skip=passes >= 3)
+    foot = n * ld * 4
+    ceil = stream_read_ceiling(torch, aco, foot)
+    roofline = {"bound": "mall" if foot > (4 << 20) else "l2", "achieved": round(achieved, 1),
+                "peak": ceil["GBps"], "unit": "GB/s", "frac": round(achieved / ceil["GBps"], 4),
+                "traffic": None, "kernel": f"k_construct<{tile},{passes}>",
+                "algorithmic_bytes_per_launch": alg,
+                "peak_note": (f"measured: streaming read of a {foot / 1e6:.1f} MB buffer (the "
+                              f"choice matrix's footprint), every XCD walking all of it, best of "
+                              f"{len(PROBE_SHAPES)} load shapes (aco_probe_read_shape: "
+                              f"{ceil['loads_in_flight']} loads in flight"
+                              f"{', nontemporal' if ceil['nontemporal'] else ''}, "
+                              f"{ceil['reps']} passes, {ceil['ms']} ms)"),
+                "peak_by_shape_GBps": ceil["by_shape_GBps"],
+                "hbm_peak": HBM_PEAK_GBPS, "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBPS, 4),
+                "requested_bytes_per_launch": req,
+                "requested_GBps": round(req / (con_ms * 1e-3) / 1e9, 1),
+                "frac_requested": round(req / (con_ms * 1e-3) / 1e9 / ceil["GBps"], 4)}
+    if main:
+        traffic, traffic_note = traffic_from_profile()
+        roofline["traffic"] = traffic
+        roofline["traffic_note"] = traffic_note
+
+    upd = {}
+    for kind, ms in t_upd_v.items():
+        b = UPDATE_BYTES[kind](n, m)
+        upd[kind] = {"ms": round(ms, 4), "algorithmic_bytes": b,
+                     "GBps": round(b / (ms * 1e-3) / 1e9, 1)}
+    rec = {
+        "metric": METRIC,
+        "value": round(ant_steps / (ms_step * 1e-3), 1),
+        "unit": "ant-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Ant System, n={n} cities {wl['layout']} in "
+                               f"[0,{wl['side']}]^2 (instance seed {wl['seed']}), m={m} ants, "
+                               f"alpha={ALPHA}, beta={BETA}, rho={RHO}, Philox seed 1, "
+                               f"{args.update} update; one step = one iteration",
+                   "n": n, "m": m, "layout": wl["layout"], "update": args.update},
+        "construct_ms": round(con_ms, 4),
+        "construct_ant_steps_per_s": round(ant_steps / (con_ms * 1e-3), 1),
+        "update": upd,
+        "best_len_after_run": int(best_len),
+        "roofline": roofline,
+    }
+    if main:
+        # each update kernel against a copy of its own footprint (one launch)
+        for kind in upd:
+            b = upd[kind]["algorithmic_bytes"]
+            cc = copy_ceiling(torch, aco, b)
+            upd[kind]["roofline"] = {
+                "bound": "mall" if b < (256 << 20) else "hbm", "achieved": upd[kind]["GBps"],
+                "peak": cc["GBps"], "unit": "GB/s",
+                "frac": round(upd[kind]["GBps"] / cc["GBps"], 4),
+                "peak_note": (f"measured: one aco_probe_copy launch over {b / 1e6:.1f} MB (half "
+                              f"read, half written), mean of 20 launches, "
+                              f"{cc['ms_per_launch']} ms each"),
+                "hbm_peak": HBM_PEAK_GBPS,
+                "frac_of_hbm_peak": round(upd[kind]["GBps"] / HBM_PEAK_GBPS, 4)}
+    return rec, d
 
 
 def main():
@@ -572,14 +816,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch256", "served"],
-                    default="n2400")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["batch256", "served", "all"],
+                    default="all",
+                    help="all (default): the n = 2400 line with every other workload as a "
+                         "sub-record; otherwise that workload alone")
     ap.add_argument("--requests", type=int, default=100, help="served workload: trace length")
     ap.add_argument("--slots", type=int, default=32, help="served workload: server slots")
-    ap.add_argument("--update", choices=["gather", "atomic"], default="gather")
+    ap.add_argument("--update", choices=["gather", "atomic", "atomic_direct"], default="gather")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="host time budget of the oracle sample (0 skips it)")
-    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the HBM and 160 MB streaming probes and the random-row probes")
     ap.add_argument("--sync-launches", action="store_true",
                     help="synchronise with the host after every launch (for profiled runs; "
                          "ms_per_step then includes the round trips)")
@@ -604,132 +851,60 @@ def main():
     from paper_1101_2678_amd import aco
 
     if args.workload == "batch256":
-        bench_batch(args, torch, aco)
+        print(json.dumps(bench_batch(args, torch, aco)), flush=True)
         return
     if args.workload == "served":
-        bench_served(args, torch, aco)
+        print(json.dumps(bench_served(args, torch, aco)), flush=True)
         return
-    wl = WORKLOADS[args.workload]
-    n, m = wl["n"], wl["m"]
-    _, d = tsp_inputs.instance(n, wl["layout"], side=wl["side"], seed=wl["seed"])
-    col = aco.Colony(d, m, ALPHA, BETA, RHO, seed=1, atomic=True)
-    stream = torch.cuda.current_stream()
-    log(f"bench: {args.workload} n={n} m={m} {col.describe()}")
+    if args.workload != "all":
+        rec, _ = run_single(args, torch, aco, args.workload, args.steps, args.warmup, main=False)
+        print(json.dumps(rec), flush=True)
+        return
 
-    it = 0
-    for _ in range(args.warmup):
-        col.construct(it)
-        launched(torch)
-        col.update(args.update)
-        launched(torch)
-        it += 1
-    torch.cuda.synchronize()
-
-    K = args.steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(K):
-        ev[3 * s].record(stream)
-        col.construct(it)
-        launched(torch)
-        ev[3 * s + 1].record(stream)
-        col.update(args.update)
-        launched(torch)
-        ev[3 * s + 2].record(stream)
-        it += 1
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t_con = np.array([ev[3 * s].elapsed_time(ev[3 * s + 1]) for s in range(K)])
-    t_upd = np.array([ev[3 * s + 1].elapsed_time(ev[3 * s + 2]) for s in range(K)])
-    log(f"bench: timed {K} steps in {wall:.3f} s")
-
-    # the other update variant, timed after the timed region on the same state
-    other = "atomic" if args.update == "gather" else "gather"
-    t_other = []
-    for _ in range(max(3, min(K, 10))):
-        col.construct(it)
-        launched(torch)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        col.update(other)
-        launched(torch)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_other.append(e0.elapsed_time(e1))
-        it += 1
-    t_upd_v = {args.update: float(t_upd.mean()), other: float(np.mean(t_other))}
-    best_tour, best_len = col.best()
-    col.close()
-
-    probe = None if args.no_probe else probe_bandwidth(torch, aco, n, m)
-    product_rec = None
+    rec, d = run_single(args, torch, aco, "n2400", args.steps, args.warmup, main=True)
+    n, m = rec["config"]["n"], rec["config"]["m"]
+    if not args.no_probe:
+        log("bench: HBM and 160 MB streaming probes, random-row probes")
+        rec["probe"] = {
+            "stream_read_4GiB": stream_read_ceiling(torch, aco, 4 << 30),
+            "stream_read_160MB": stream_read_ceiling(torch, aco, 160 << 20),
+            "random_rows_same_footprint_GBps": random_rows_rate(torch, aco, n, m, n),
+            "random_rows_160MB_GBps": random_rows_rate(torch, aco, n, m,
+                                                       (160 << 20) // (4 * ((n + 63) // 64 * 64))),
+            "hbm_peak_GBps": HBM_PEAK_GBPS,
+        }
     if not args.no_product:
         log("bench: product-and-argmax construction")
-        product_rec = bench_product(torch, aco, d, m, K, args.warmup, args.update,
-                                    min(3.0, args.cpu_seconds))
-    nn_rec = None
+        rec["product"] = bench_product(torch, aco, d, m, args.steps, args.warmup, args.update,
+                                       min(3.0, args.cpu_seconds))
     if args.nn > 0:
         log(f"bench: candidate-list construction, nn={args.nn}")
-        nn_rec = bench_nn(torch, aco, d, m, args.nn, K, args.warmup, args.update,
-                          min(3.0, args.cpu_seconds))
-
-    ant_steps = m * (n - 1)
-    ms_step = wall * 1e3 / K
-    con_ms = float(t_con.mean())
-    achieved = construct_bytes(n, m) / (con_ms * 1e-3) / 1e9
-    traffic, traffic_note = traffic_from_profile()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": traffic, "kernel": "k_construct",
-                "algorithmic_bytes_per_launch": construct_bytes(n, m),
-                "traffic_note": traffic_note}
-    if probe:
-        ceiling = probe["random_rows_same_footprint_GBps"]
-        roofline["measured_random_row_ceiling_GBps"] = ceiling
-        roofline["frac_of_measured_random_row_ceiling"] = round(achieved / ceiling, 4)
-
-    cpu = None
+        rec["nn_list"] = bench_nn(torch, aco, d, m, args.nn, args.steps, args.warmup,
+                                  args.update, min(3.0, args.cpu_seconds))
+    configs = {}
+    for name in ("n100", "n1000u", "n1000c"):
+        configs[name], _ = run_single(args, torch, aco, name, args.steps, args.warmup,
+                                      main=False)
+    log("bench: batch256")
+    configs["batch256"] = bench_batch(args, torch, aco)
+    log("bench: served")
+    configs["served"] = bench_served(args, torch, aco)
+    rec["configs"] = configs
+    srv = configs["served"]
+    rec["served_solves_per_s"] = srv["value"]
+    rec["served_latency_p50_s"] = srv["latency_p50_s"]
+    rec["served_latency_p99_s"] = srv["latency_p99_s"]
+    rec["served_plain_solves_per_s"] = round(srv["plain_one_request_at_a_time"]["solves_per_s"], 3)
+    rec["served_plain_latency_p99_s"] = round(
+        srv["plain_one_request_at_a_time"]["latency_p99_s"], 4)
+    rec["batch256_solves_per_s"] = configs["batch256"]["value"]
+    rec["batch256_one_per_launch_solves_per_s"] = (
+        configs["batch256"]["one_instance_per_launch"]["solves_per_s"])
     if args.cpu_seconds > 0:
         log(f"bench: timing the oracle (up to ~{args.cpu_seconds:.0f} s of host work)")
-        cpu = cpu_baseline(d, m, args.cpu_seconds)
-
-    rec = {
-        "metric": METRIC,
-        "value": round(ant_steps / (ms_step * 1e-3), 1),
-        "unit": "ant-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"Ant System, n={n} cities {wl['layout']} in "
-                               f"[0,{wl['side']}]^2 (instance seed {wl['seed']}), m={m} ants, "
-                               f"alpha={ALPHA}, beta={BETA}, rho={RHO}, Philox seed 1, "
-                               f"{args.update} update; one step = one iteration",
-                   "n": n, "m": m, "layout": wl["layout"], "update": args.update},
-        "construct_ms": round(con_ms, 4),
-        "construct_ant_steps_per_s": round(ant_steps / (con_ms * 1e-3), 1),
-        "update_ms": {k: round(v, 4) for k, v in t_upd_v.items()},
-        "update_GBps": {
-            "gather": round(gather_bytes(n, m) / (t_upd_v["gather"] * 1e-3) / 1e9, 1),
-            "atomic": round(atomic_bytes(n, m) / (t_upd_v["atomic"] * 1e-3) / 1e9, 1)},
-        "update_frac_of_hbm_peak": {
-            "gather": round(gather_bytes(n, m) / (t_upd_v["gather"] * 1e-3) / 1e9
-                            / HBM_PEAK_GBPS, 4),
-            "atomic": round(atomic_bytes(n, m) / (t_upd_v["atomic"] * 1e-3) / 1e9
-                            / HBM_PEAK_GBPS, 4)},
-        "best_len_after_run": int(best_len),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "probe": probe,
-        "nn_list": nn_rec,
-        "product": product_rec,
-    }
+        rec["cpu_baseline"] = cpu_baseline(d, m, args.cpu_seconds)
+    else:
+        rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)
 
 

@@ -67,9 +67,21 @@ typedef enum {
     ACO_ERR_STATE = 4    /* call out of order, or context poisoned */
 } aco_status;
 
+/* Pheromone update variants (Section III-B); all three give the same bits.
+ *   GATHER         scatter-to-gather: one workgroup owns row i, reads the tour
+ *                  neighbours of city i in every ant's tour and writes the
+ *                  row; no global atomics.
+ *   ATOMIC         one thread per city of an ant's tour, deposits combined in
+ *                  shared memory (LDS) per row, then one global binary64
+ *                  atomic per distinct edge ("atomic instructions + shared
+ *                  memory", the paper's fastest update).
+ *   ATOMIC_DIRECT  one global binary64 atomic per tour edge ("atomic
+ *                  instructions").
+ * Both atomic kinds need the atomic part of the workspace. */
 typedef enum {
-    ACO_UPDATE_GATHER = 0, /* scatter-to-gather: one workgroup owns a row */
-    ACO_UPDATE_ATOMIC = 1  /* one thread per tour edge, binary64 atomics */
+    ACO_UPDATE_GATHER = 0,
+    ACO_UPDATE_ATOMIC = 1,
+    ACO_UPDATE_ATOMIC_DIRECT = 2
 } aco_update_kind;
 
 /* Problem and AS parameters.
@@ -125,8 +137,8 @@ aco_status aco_construct(aco_ctx* c, uint32_t iter);
  * among equals, replaces the stored one only if strictly shorter), then the
  * pheromone update (Eqs. 2-4) from those tours and the choice refresh.
  * Asynchronous.  ACO_ERR_STATE if no construction preceded
- * it since the last update; ACO_ERR_INVALID for ACO_UPDATE_ATOMIC without the
- * atomic workspace. */
+ * it since the last update; ACO_ERR_INVALID for an atomic kind without the
+ * atomic workspace or an unknown kind. */
 aco_status aco_update(aco_ctx* c, aco_update_kind kind);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -325,6 +337,42 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
  * non-default stream.  Asynchronous. */
 aco_status aco_batch_run(aco_batch* b, uint32_t iters, int32_t use_graph);
 
+/* Launch configuration of a batch's construction.  It changes speed only,
+ * never results (the paper's tiling and block-size choices, Section III-A).
+ *   wg_per_cu    at most this many construction workgroups (ants) resident
+ *                on a compute unit, enforced through the workgroup's LDS
+ *                request (the device's LDS per CU / wg_per_cu); 0 = no cap
+ *                (registers and LDS of the tour decide).  Each resident ant
+ *                keeps one choice row in flight: more of them evict one
+ *                another's rows from the L2, fewer leave its latency bare.
+ *   tile4_max_n  instances with n <= tile4_max_n use 4 cities per lane and
+ *                pass, the others 8 (at most 1024); -1 = the process-wide
+ *                tile table (aco_set_tile / aco_autotune).
+ * Default after aco_batch_init: tile4_max_n = -1, and wg_per_cu = 16 when
+ * the batch has at least 8 * 16 ants per compute unit, else 0. */
+typedef struct {
+    int32_t wg_per_cu;
+    int32_t tile4_max_n;
+} aco_batch_config;
+
+/* Sets the launch configuration; waits for the batch's stream and drops a
+ * captured graph (the next graph run captures again).  ACO_ERR_INVALID if
+ * wg_per_cu is outside [0, 64] or asks for more LDS than one workgroup may
+ * hold, or tile4_max_n is outside [-1, 1024].  Synchronous. */
+aco_status aco_batch_set_config(aco_batch* b, const aco_batch_config* cfg);
+aco_status aco_batch_get_config(aco_batch* b, aco_batch_config* cfg);
+
+/* Autotuner of the batched launch: for each of the `count` candidate
+ * configurations (host array), one warm-up iteration and then `iters` timed
+ * iterations of the whole batch (eager launches, HIP events on the batch's
+ * stream); keeps the fastest configuration.  best_index (host, may be NULL)
+ * receives its index, ms_per_iter (count floats, host, may be NULL) every
+ * candidate's time per iteration.  Advances every instance by
+ * count * (iters + 1) iterations, computed exactly as any other iterations
+ * of the batch.  Synchronous. */
+aco_status aco_batch_autotune(aco_batch* b, const aco_batch_config* cands, int32_t count,
+                              uint32_t iters, int32_t* best_index, float* ms_per_iter);
+
 /* Per-instance reads (q in caller order).  Synchronous. */
 aco_status aco_batch_read_best(aco_batch* b, int32_t q, uint16_t* best_tour_host,
                                int64_t* best_len_host);
@@ -351,6 +399,14 @@ aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void
  * by HBM.  Algorithmic bytes: bytes * reps.  Asynchronous. */
 aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float* sink_dev,
                           void* hip_stream);
+
+/* aco_probe_read with a chosen load shape: loads_in_flight 16-byte loads per
+ * thread issued before any is used (4, 8 or 16; aco_probe_read uses 4), and
+ * nontemporal != 0 for loads that keep nothing in the caches.  The streaming
+ * ceiling of a footprint is the best rate over the shapes.  Async. */
+aco_status aco_probe_read_shape(const void* src_dev, size_t bytes, int32_t reps,
+                                int32_t loads_in_flight, int32_t nontemporal, float* sink_dev,
+                                void* hip_stream);
 
 /* ---- serving: continuous batching of independent solves ------------------ */
 

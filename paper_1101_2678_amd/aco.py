@@ -16,14 +16,19 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libaco.so")
 
 ACO_OK, ACO_ERR_INVALID, ACO_ERR_NOMEM, ACO_ERR_DEVICE, ACO_ERR_STATE = range(5)
-GATHER, ATOMIC = 0, 1
-_KIND = {"gather": GATHER, "atomic": ATOMIC, GATHER: GATHER, ATOMIC: ATOMIC}
+GATHER, ATOMIC, ATOMIC_DIRECT = 0, 1, 2
+_KIND = {"gather": GATHER, "atomic": ATOMIC, "atomic_direct": ATOMIC_DIRECT, GATHER: GATHER,
+         ATOMIC: ATOMIC, ATOMIC_DIRECT: ATOMIC_DIRECT}
 
 
 class AcoError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status} ({detail})")
         self.status = status
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("tile4_max_n", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +90,9 @@ def _load():
         "aco_batch_read_tau": (i32, [vp, i32, vp]),
         "aco_batch_get_iter": (i32, [vp, i32, c.POINTER(u32)]),
         "aco_batch_sync": (i32, [vp]),
+        "aco_batch_set_config": (i32, [vp, c.POINTER(BatchConfig)]),
+        "aco_batch_get_config": (i32, [vp, c.POINTER(BatchConfig)]),
+        "aco_batch_autotune": (i32, [vp, vp, i32, u32, c.POINTER(i32), vp]),
         "aco_batch_destroy": (None, [vp]),
         "aco_server_table_bytes": (sz, [i32, i32, i32, i32]),
         "aco_server_create": (i32, [c.POINTER(vp), vp, sz, i32, i32, i32, i32, vp]),
@@ -99,6 +107,7 @@ def _load():
         "aco_server_destroy": (None, [vp]),
         "aco_probe_copy": (i32, [vp, vp, sz, vp]),
         "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
+        "aco_probe_read_shape": (i32, [vp, sz, i32, i32, i32, vp, vp]),
         "aco_probe_rows": (i32, [vp, i32, i32, i32, i32, i32, vp, vp]),
         "aco_probe_philox": (i32, [i32, i32, u32, vp, vp]),
     }
@@ -397,6 +406,27 @@ class Batch:
     def sync(self):
         _check(lib.aco_batch_sync(self._b), "aco_batch_sync")
 
+    @property
+    def config(self) -> dict:
+        cfg = BatchConfig()
+        _check(lib.aco_batch_get_config(self._b, ctypes.byref(cfg)), "aco_batch_get_config")
+        return {"wg_per_cu": int(cfg.wg_per_cu), "tile4_max_n": int(cfg.tile4_max_n)}
+
+    def set_config(self, wg_per_cu: int, tile4_max_n: int = -1):
+        cfg = BatchConfig(wg_per_cu, tile4_max_n)
+        _check(lib.aco_batch_set_config(self._b, ctypes.byref(cfg)), "aco_batch_set_config")
+
+    def autotune(self, candidates, iters: int = 2):
+        """candidates: (wg_per_cu, tile4_max_n) pairs.  Times each on this
+        batch (advancing it, see aco_batch_autotune) and keeps the fastest;
+        returns (best index, ms per iteration of every candidate)."""
+        arr = (BatchConfig * len(candidates))(*[BatchConfig(w, t) for w, t in candidates])
+        best = ctypes.c_int32(-1)
+        ms = np.zeros(len(candidates), np.float32)
+        _check(lib.aco_batch_autotune(self._b, arr, len(candidates), iters, ctypes.byref(best),
+                                      ms.ctypes.data_as(ctypes.c_void_p)), "aco_batch_autotune")
+        return int(best.value), ms
+
     def best(self, q: int):
         n = self._dists[q].shape[0]
         tour = np.empty(n + 1, np.uint16)
@@ -459,7 +489,8 @@ def probe_philox(waves: int, steps: int, seed: int, sink, stream=None):
                                 _stream_handle(stream)), "aco_probe_philox")
 
 
-def probe_read(src, reps: int, sink, stream=None):
-    _check(lib.aco_probe_read(ctypes.c_void_p(src.data_ptr()), src.numel() * src.element_size(),
-                              reps, ctypes.c_void_p(sink.data_ptr()), _stream_handle(stream)),
-           "aco_probe_read")
+def probe_read(src, reps: int, sink, stream=None, loads: int = 4, nontemporal: bool = False):
+    _check(lib.aco_probe_read_shape(ctypes.c_void_p(src.data_ptr()),
+                                    src.numel() * src.element_size(), reps, loads,
+                                    1 if nontemporal else 0, ctypes.c_void_p(sink.data_ptr()),
+                                    _stream_handle(stream)), "aco_probe_read_shape")

@@ -194,6 +194,18 @@ int8_t* tile_table() {
 
 void reset_tiles() { fill_default_tiles(tile_table()); }
 
+hipError_t device_shape(int* cus, size_t* lds_per_cu) {
+    int dev = 0, n_cu = 0, lds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e != hipSuccess) return e;
+    *cus = n_cu;
+    *lds_per_cu = (size_t)lds;
+    return hipSuccess;
+}
+
 int tile_for(int n) {
     return (n >= 0 && n <= kMaxCities) ? tile_table()[n] : 8;
 }
@@ -250,7 +262,7 @@ aco_status enqueue_update(aco_ctx* c, aco_update_kind kind, double* delta) {
     } else {
         Colony col = c->col;
         if (delta) col.delta = delta;
-        e = launch_update_atomic(col, c->stream);
+        e = launch_update_atomic(col, kind == ACO_UPDATE_ATOMIC, c->stream);
     }
     if (e != hipSuccess) return ::device_fail(c, e, "aco_update");
     c->pending = false;
@@ -345,9 +357,9 @@ aco_status aco_construct(aco_ctx* c, uint32_t iter) {
 
 aco_status aco_update(aco_ctx* c, aco_update_kind kind) {
     if (aco_status s = aco::host::update_ready(c)) return s;
-    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
+    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC && kind != ACO_UPDATE_ATOMIC_DIRECT)
         return fail(ACO_ERR_INVALID, "unknown update kind");
-    if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
+    if (kind != ACO_UPDATE_GATHER && !c->has_atomic)
         return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
     return aco::host::enqueue_update(c, kind, nullptr);
 }
@@ -356,10 +368,10 @@ static aco_status solve_with(aco_ctx* c, uint32_t iters, aco_update_kind kind,
                              aco_status (*construct)(aco_ctx*, uint32_t),
                              uint16_t* best_tour_host, int64_t* best_len_host) {
     if (aco_status s = usable(c)) return s;
-    if (kind == ACO_UPDATE_ATOMIC && !c->has_atomic)
-        return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
-    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC)
+    if (kind != ACO_UPDATE_GATHER && kind != ACO_UPDATE_ATOMIC && kind != ACO_UPDATE_ATOMIC_DIRECT)
         return fail(ACO_ERR_INVALID, "unknown update kind");
+    if (kind != ACO_UPDATE_GATHER && !c->has_atomic)
+        return fail(ACO_ERR_INVALID, "workspace has no room for the atomic update");
     for (uint32_t i = 0; i < iters; ++i) {
         if (aco_status s = construct(c, c->next_iter)) return s;
         if (aco_status s = aco_update(c, kind)) return s;
@@ -555,7 +567,8 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
     const int pass = 64 * col.tile;
     std::snprintf(buf, len,
                   "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
-                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 atomic=%d nn=%d",
+                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 "
+                  "atomic=%d nn=%d",
                   col.tile, (col.n + pass - 1) / pass, (col.n + 63) / 64, col.ld,
                   aco::construct_occupancy(col), cus, lds_cu, c->has_atomic ? 1 : 0, c->nn.nn);
     return ACO_OK;
@@ -595,9 +608,25 @@ aco_status aco_probe_read(const void* src_dev, size_t bytes, int32_t reps, float
     if (reps < 0) return fail(ACO_ERR_INVALID, "reps must be >= 0");
     if (bytes && (!src_dev || !sink_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
     if (((uintptr_t)src_dev % 16) != 0) return fail(ACO_ERR_INVALID, "src must be 16-byte aligned");
-    const hipError_t e = aco::launch_probe_read(src_dev, bytes, reps, sink_dev,
+    const hipError_t e = aco::launch_probe_read(src_dev, bytes, reps, 4, false, sink_dev,
                                                 static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_read");
+    return ACO_OK;
+}
+
+aco_status aco_probe_read_shape(const void* src_dev, size_t bytes, int32_t reps,
+                                int32_t loads_in_flight, int32_t nontemporal, float* sink_dev,
+                                void* hip_stream) {
+    if (bytes % 16 != 0) return fail(ACO_ERR_INVALID, "bytes must be a multiple of 16");
+    if (reps < 0) return fail(ACO_ERR_INVALID, "reps must be >= 0");
+    if (loads_in_flight != 4 && loads_in_flight != 8 && loads_in_flight != 16)
+        return fail(ACO_ERR_INVALID, "loads_in_flight must be 4, 8 or 16");
+    if (bytes && (!src_dev || !sink_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)src_dev % 16) != 0) return fail(ACO_ERR_INVALID, "src must be 16-byte aligned");
+    const hipError_t e =
+        aco::launch_probe_read(src_dev, bytes, reps, loads_in_flight, nontemporal != 0, sink_dev,
+                               static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_read_shape");
     return ACO_OK;
 }
 

@@ -38,6 +38,8 @@ Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, 
 // initialisation kernels (nearest-neighbour tour, tau0, tau and choice fill).
 hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t base_bytes,
                            hipStream_t stream);
+// Compute units and LDS bytes per compute unit of the current device.
+hipError_t device_shape(int* cus, size_t* lds_per_cu);
 int tile_for(int n);
 bool set_tile_range(int lo, int hi, int tile);
 void reset_tiles();

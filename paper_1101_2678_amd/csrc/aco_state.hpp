@@ -45,10 +45,16 @@ constexpr int kMaxNoallocCities = 1024;
 bool tile_supported(int tile, int n);
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
 // One workgroup per entry of antmap: (colony << 16) | ant.  max_n, the largest
-// n among the colonies, sizes the tour kept in LDS and picks the kernel's
-// pass bound, so it must not be smaller than any colony's n.
+// n among the colonies, picks the kernel's pass bound, so it must not be
+// smaller than any colony's n; lds (dynamic LDS per workgroup, from
+// batch_lds_bytes) holds the tour and sets how many workgroups fit a CU.
 hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
-                                  int max_n, hipStream_t s);
+                                  int max_n, size_t lds, hipStream_t s);
+// Dynamic LDS per batched construction workgroup for at most wg_per_cu
+// workgroups on a CU of lds_per_cu bytes (wg_per_cu 0: no cap, the tour only).
+size_t batch_lds_bytes(int max_n, int wg_per_cu, size_t lds_per_cu);
+// The cap a batch of total_ants ants on `cus` compute units gets by default.
+int batch_default_cap(int total_ants, int cus);
 hipError_t launch_best_batch(const Colony* cols, int count, hipStream_t s);
 // One workgroup per entry of rowmap: (colony << 16) | row.
 hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap, int total_rows,
@@ -56,7 +62,9 @@ hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap
 // Construction workgroups (ants) resident per compute unit, or -1.
 int construct_occupancy(const Colony& c);
 hipError_t launch_update_gather(const Colony& c, hipStream_t s);
-hipError_t launch_update_atomic(const Colony& c, hipStream_t s);
+// combine_in_lds: the shared-memory deposit (one global atomic per distinct
+// edge of a row's workgroup); false: one global atomic per tour edge.
+hipError_t launch_update_atomic(const Colony& c, bool combine_in_lds, hipStream_t s);
 hipError_t launch_init(const Colony& c, hipStream_t s);
 hipError_t launch_refresh_choice(const Colony& c, hipStream_t s);
 hipError_t launch_test_select(int tile, int n, int count, const float* rows,
@@ -65,7 +73,9 @@ hipError_t launch_test_select(int tile, int n, int count, const float* rows,
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
                              int steps, float* sink, hipStream_t s);
-hipError_t launch_probe_read(const void* src, size_t bytes, int reps, float* sink,
-                             hipStream_t s);
+// loads: 16-byte loads in flight per thread (4, 8 or 16); nontemporal loads
+// keep nothing in the caches.
+hipError_t launch_probe_read(const void* src, size_t bytes, int reps, int loads, bool nontemporal,
+                             float* sink, hipStream_t s);
 
 }  // namespace aco

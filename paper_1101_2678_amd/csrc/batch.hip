@@ -39,6 +39,12 @@ struct aco_batch {
     hipGraphExec_t exec = nullptr;
     uint32_t graph_iters = 0;
     bool poisoned = false;
+    // launch configuration of the construction (speed only, never results)
+    aco_batch_config config{0, -1};
+    int cus = 0;                   // compute units of the device
+    size_t lds_per_cu = 0;         // LDS bytes per compute unit
+    size_t max_lds_per_wg = 0;     // LDS bytes one workgroup may hold
+    std::vector<aco::Colony> launch_cols;  // host copy of d_cols
 };
 
 namespace {
@@ -90,8 +96,9 @@ aco_status batch_device_fail(aco_batch* b, hipError_t e, const char* where) {
 hipError_t enqueue_iterations(aco_batch* b, uint32_t iters) {
     hipError_t e = hipSuccess;
     for (uint32_t i = 0; i < iters && e == hipSuccess; ++i) {
-        e = aco::launch_construct_batch(b->d_cols, b->d_antmap, b->total_ants, b->max_n,
-                                        b->stream);
+        e = aco::launch_construct_batch(
+            b->d_cols, b->d_antmap, b->total_ants, b->max_n,
+            aco::batch_lds_bytes(b->max_n, b->config.wg_per_cu, b->lds_per_cu), b->stream);
         if (e == hipSuccess) e = aco::launch_best_batch(b->d_cols, b->count, b->stream);
         if (e == hipSuccess)
             e = aco::launch_update_gather_batch(b->d_cols, b->d_rowmap, b->total_rows, b->max_ld,
@@ -177,8 +184,19 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
         return fail(ACO_ERR_DEVICE, "aco_batch_init: no current HIP device");
     if (aco_status s = aco::host::stream_on_device(hip_stream, device, "aco_batch_init")) return s;
 
+    int cus = 0, max_wg_lds = 0;
+    size_t lds_per_cu = 0;
+    if (aco::host::device_shape(&cus, &lds_per_cu) != hipSuccess ||
+        hipDeviceGetAttribute(&max_wg_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+            hipSuccess)
+        return fail(ACO_ERR_DEVICE, "aco_batch_init: device attributes unavailable");
     aco_batch* b = new (std::nothrow) aco_batch();
     if (!b) return fail(ACO_ERR_NOMEM, "host allocation failed");
+    b->cus = cus;
+    b->lds_per_cu = lds_per_cu;
+    b->max_lds_per_wg = (size_t)max_wg_lds;
+    b->config.wg_per_cu = aco::batch_default_cap(B.total_ants, cus);
+    b->config.tile4_max_n = -1;
     char* base = static_cast<char*>(d_workspace);
     b->count = count;
     b->stream = static_cast<hipStream_t>(hip_stream);
@@ -195,7 +213,8 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
     for (int q = 0; q < count; ++q) b->order[q] = q;
     std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int a, int c) { return params[a].n > params[c].n; });
-    std::vector<aco::Colony> launch_cols(count);
+    std::vector<aco::Colony>& launch_cols = b->launch_cols;
+    launch_cols.resize(count);
     std::vector<uint32_t> antmap, rowmap;
     antmap.reserve(B.total_ants);
     rowmap.reserve(B.total_rows);
@@ -325,6 +344,86 @@ void aco_batch_destroy(aco_batch* b) {
     if (!b) return;
     drop_graph(b);
     delete b;
+}
+
+aco_status aco_batch_set_config(aco_batch* b, const aco_batch_config* cfg) {
+    if (aco_status s = batch_usable(b)) return s;
+    if (!cfg) return fail(ACO_ERR_INVALID, "config is NULL");
+    if (cfg->wg_per_cu < 0 || cfg->wg_per_cu > 64)
+        return fail(ACO_ERR_INVALID, "wg_per_cu must be in [0, 64]");
+    if (aco::batch_lds_bytes(b->max_n, cfg->wg_per_cu, b->lds_per_cu) > b->max_lds_per_wg)
+        return fail(ACO_ERR_INVALID, "wg_per_cu asks for more LDS than one workgroup may hold");
+    if (cfg->tile4_max_n < -1 || cfg->tile4_max_n > aco::kMaxTile4Cities)
+        return fail(ACO_ERR_INVALID, "tile4_max_n must be in [-1, 1024]");
+    // the graph holds the old launch shape; a replay still queued reads d_cols
+    drop_graph(b);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (int pos = 0; pos < b->count; ++pos) {
+        const int q = b->order[pos];
+        const int n = b->cols[q].n;
+        const int tile = cfg->tile4_max_n < 0 ? aco::host::tile_for(n)
+                                              : (n <= cfg->tile4_max_n ? 4 : 8);
+        b->cols[q].tile = tile;
+        b->launch_cols[pos].tile = tile;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_cols, b->launch_cols.data(), sizeof(aco::Colony) * b->count,
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_set_config");
+    b->config = *cfg;
+    return ACO_OK;
+}
+
+aco_status aco_batch_get_config(aco_batch* b, aco_batch_config* cfg) {
+    if (aco_status s = batch_usable(b)) return s;
+    if (!cfg) return fail(ACO_ERR_INVALID, "config is NULL");
+    *cfg = b->config;
+    return ACO_OK;
+}
+
+aco_status aco_batch_autotune(aco_batch* b, const aco_batch_config* cands, int32_t count,
+                              uint32_t iters, int32_t* best_index, float* ms_per_iter) {
+    if (aco_status s = batch_usable(b)) return s;
+    if (!cands || count < 1) return fail(ACO_ERR_INVALID, "need at least one candidate");
+    if (iters < 1) return fail(ACO_ERR_INVALID, "iters must be >= 1");
+    for (int i = 0; i < count; ++i) {
+        if (cands[i].wg_per_cu < 0 || cands[i].wg_per_cu > 64 ||
+            aco::batch_lds_bytes(b->max_n, cands[i].wg_per_cu, b->lds_per_cu) > b->max_lds_per_wg ||
+            cands[i].tile4_max_n < -1 || cands[i].tile4_max_n > aco::kMaxTile4Cities)
+            return fail(ACO_ERR_INVALID, "candidate " + std::to_string(i) + " is out of range");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = 0;
+    float t_best = 1e30f;
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+        if (aco_status s = aco_batch_set_config(b, &cands[i])) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return s;
+        }
+        e = enqueue_iterations(b, 1);  // warm-up at this shape
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess) e = enqueue_iterations(b, iters);
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        ms /= (float)iters;
+        if (ms_per_iter) ms_per_iter[i] = ms;
+        if (ms < t_best) {
+            t_best = ms;
+            best = i;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return batch_device_fail(b, e, "aco_batch_autotune");
+    if (best_index) *best_index = best;
+    return aco_batch_set_config(b, &cands[best]);
 }
 
 aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes, int32_t count,

@@ -151,21 +151,15 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
     }
 }
 
-// One R64 roulette draw over `row` (ld-padded, zero beyond n), with np <= P
-// passes in use (np == P when GUARD is false).  Returns the chosen city, or
-// -1 if no city is feasible.  Wave-uniform.
-// The masked weights stay in registers; the pass holding a candidate block
-// is staged into LDS only when that block is scanned.  The workgroup is one
-// wavefront: its LDS operations execute in program order, and every LDS
-// access below uses a lane-dependent index, so the compiler keeps the order.
+// Issues the loads of one choice row (ld-padded, zero beyond n) into wa/wb:
+// in pass p < np lane l takes cities 64Gp + Gl .. + G - 1.  With SKIP, a
+// 16-byte load whose four cities are all visited goes out of range instead
+// (it returns zeros and touches no memory).
 template <int G, int P, bool GUARD, bool SKIP>
-__device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
-                                        uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
-                                        float* s_w, float u, int lane) {
-    constexpr int LPB = Tile<G>::kLanesPerBlock;
-    const int nb = (n + 63) >> 6;
+__device__ __forceinline__ void load_row(const float* __restrict__ row, int n, int np,
+                                         uint64_t lane_bits, int lane, u32x4 (&wa)[P],
+                                         u32x4 (&wb)[P]) {
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
-    u32x4 wa[P], wb[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (GUARD && p >= np) break;
@@ -178,6 +172,22 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, in
             wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, ob, 0, 0);
         }
     }
+}
+
+// One R64 roulette draw over a loaded row (wa/wb as load_row leaves them;
+// masked in place), with np <= P passes in use (np == P when GUARD is
+// false).  Returns the chosen city, or -1 if no city is feasible.
+// Wave-uniform.  The masked weights stay in registers; the pass holding a
+// candidate block is staged into LDS only when that block is scanned.  The
+// workgroup is one wavefront: its LDS operations execute in program order,
+// and every LDS access below uses a lane-dependent index, so the compiler
+// keeps the order.
+template <int G, int P, bool GUARD>
+__device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n, int np,
+                                           uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
+                                           float* s_w, float u, int lane) {
+    constexpr int LPB = Tile<G>::kLanesPerBlock;
+    const int nb = (n + 63) >> 6;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (GUARD && p >= np) break;
@@ -217,6 +227,15 @@ __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, in
     if (!live) return -1;
     const int b = 63 - __builtin_clzll(live);
     return b * 64 + 63 - __builtin_clzll(~s_vis[b]);
+}
+
+template <int G, int P, bool GUARD, bool SKIP>
+__device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
+                                        uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
+                                        float* s_w, float u, int lane) {
+    u32x4 wa[P], wb[P];
+    load_row<G, P, GUARD, SKIP>(row, n, np, lane_bits, lane, wa, wb);
+    return pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, s_vis, s_T, s_w, u, lane);
 }
 
 // Uniform draws for steps s0 .. s0+63: lane t holds u of step s0 + t.  The
@@ -290,6 +309,10 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     }
 }
 
+__host__ __device__ size_t tour_lds_bytes(int n) {
+    return ((size_t)(n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
+}
+
 template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
@@ -350,31 +373,35 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
     if (lane == 0) out[q] = j;
 }
 
-size_t tour_lds_bytes(int n) { return ((size_t)(n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15; }
-
-// Batched launches hold at most kBatchWgPerCu workgroups per CU, by asking
-// for more dynamic LDS than the tour needs.  Each workgroup keeps one choice
-// row in flight; with more of them the rows evict one another from the L2 of
-// each XCD, with fewer the latency of a step is no longer covered.  On a
-// 256-instance batch (n 50..1000) 16 per CU gave the highest throughput: 18
-// and 20 were 0.7% and 0.6% slower, 24 2.5%, 32 (no cap) 8.7%, 14 2.1% and
-// 12 13.5%.
-// The cap only pays when the launch runs many rounds of workgroups anyway:
-// a launch that fits the device in a round or two would only gain a tail, so
-// it is capped only from kCapRounds rounds at the cap up.
+// Batched launches can hold at most `wg_per_cu` workgroups on a compute unit
+// by asking for more dynamic LDS than the tour needs.  Each workgroup keeps
+// one choice row in flight; with more of them the rows evict one another
+// from the L2 of each XCD, with fewer the latency of a step is no longer
+// covered.  The cap is part of a batch's launch configuration, chosen by the
+// batch autotuner; the default (used by the server) caps at 16 per CU, the
+// best of a manual sweep on a 256-instance batch (n 50..1000: 18 and 20 were
+// 0.7% and 0.6% slower, 24 2.5%, no cap 8.7%, 14 2.1%, 12 13.5%), and only
+// launches of at least kCapRounds rounds at the cap: one that fits the
+// device in a round or two would only gain a tail.
 constexpr int kBatchWgPerCu = 16;
 constexpr int kCapRounds = 8;
-constexpr int kCus = 256;                 // MI355X
-constexpr size_t kLdsPerCu = 160 * 1024;  // gfx950
 
-size_t batch_lds_bytes(int max_n, int total_ants) {
-    if (total_ants < kCapRounds * kBatchWgPerCu * kCus) return tour_lds_bytes(max_n);
-    const size_t per_wg = kLdsPerCu / kBatchWgPerCu;
-    const size_t fixed = sizeof(AntShared) + 64;  // static LDS and its alignment
-    const size_t cap = (per_wg - fixed) & ~(size_t)255;
+}  // namespace
+
+size_t batch_lds_bytes(int max_n, int wg_per_cu, size_t lds_per_cu) {
     const size_t tour = tour_lds_bytes(max_n);
+    if (wg_per_cu <= 0 || lds_per_cu == 0) return tour;
+    const size_t per_wg = lds_per_cu / (size_t)wg_per_cu;
+    const size_t fixed = sizeof(AntShared) + 64;  // static LDS and its alignment
+    const size_t cap = per_wg > fixed ? (per_wg - fixed) & ~(size_t)255 : 0;
     return tour > cap ? tour : cap;
 }
+
+int batch_default_cap(int total_ants, int cus) {
+    return total_ants >= kCapRounds * kBatchWgPerCu * cus ? kBatchWgPerCu : 0;
+}
+
+namespace {
 
 // Calls f.template operator()<G, P>() for the tile and pass count of n.
 template <typename F>
@@ -430,12 +457,12 @@ hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s) {
 }
 
 hipError_t launch_construct_batch(const Colony* cols, const uint32_t* antmap, int total_ants,
-                                  int max_n, hipStream_t s) {
+                                  int max_n, size_t lds, hipStream_t s) {
     if (total_ants <= 0) return hipSuccess;
     if (max_n < 1 || max_n > kMaxCities) return hipErrorInvalidValue;
+    if (lds < tour_lds_bytes(max_n)) return hipErrorInvalidValue;
     const int passes = (max_n + 511) / 512;
     const dim3 grid(total_ants), block(64);
-    const size_t lds = batch_lds_bytes(max_n, total_ants);
     if (passes <= 2)
         hipLaunchKernelGGL(k_construct_batch<2>, grid, block, lds, s, cols, antmap);
     else if (passes <= 4)

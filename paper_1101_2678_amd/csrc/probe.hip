@@ -13,35 +13,41 @@ __global__ __launch_bounds__(256) void k_probe_copy(float4* __restrict__ dst,
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
 }
 
-// Streaming read of a buffer `reps` times.  The buffer is cut into 16 KB
-// chunks (256 threads x 4 loads of 16 bytes, all four in flight before any
-// is used).  Workgroups go to the eight XCDs round-robin by index, so work
-// item w runs on XCD w mod 8; XCD x walks the whole buffer chunk by chunk,
-// starting x/8 of the way in.  Every XCD's L2 therefore sees the whole
-// footprint cycling through it, as in tour construction, where every XCD
-// reads rows from the whole choice matrix: a footprint above the L2 is
-// served from the Infinity Cache (MALL) or HBM, one below it from the L2.
-// The sum keeps the loads alive and goes to sink[blockIdx.x].
+// Streaming read of a buffer `reps` times.  The buffer is cut into chunks of
+// 256 threads x L loads of 16 bytes, all L in flight before any is used
+// (NT: nontemporal loads, which do not keep the lines in the caches).
+// Workgroups go to the eight XCDs round-robin by index, so work item w runs
+// on XCD w mod 8; XCD x walks the whole buffer chunk by chunk, starting x/8
+// of the way in.  Every XCD's L2 therefore sees the whole footprint cycling
+// through it, as in tour construction, where every XCD reads rows from the
+// whole choice matrix: a footprint above the L2 is served from the Infinity
+// Cache (MALL) or HBM, one below it from the L2.  The sum keeps the loads
+// alive and goes to sink[blockIdx.x].
 constexpr int kStreamThreads = 256;
-constexpr int kStreamLoads = 4;
-constexpr size_t kStreamChunk16 = (size_t)kStreamThreads * kStreamLoads;  // 16-byte units
 
+template <int L, bool NT>
 __global__ __launch_bounds__(kStreamThreads) void k_probe_read(const float4* __restrict__ src,
                                                                size_t n16, size_t chunks,
                                                                size_t items, float* sink) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    constexpr size_t kChunk16 = (size_t)kStreamThreads * L;  // 16-byte units
     float acc = 0.0f;
     for (size_t w = blockIdx.x; w < items; w += gridDim.x) {
         const size_t x = w & 7, k = w >> 3;
         const size_t c = (k + x * (chunks / 8 + 1)) % chunks;
-        const size_t base = c * kStreamChunk16 + threadIdx.x;
-        float4 v[kStreamLoads];
+        const size_t base = c * kChunk16 + threadIdx.x;
+        f4v v[L];
 #pragma unroll
-        for (int u = 0; u < kStreamLoads; ++u) {
+        for (int u = 0; u < L; ++u) {
             const size_t i = base + (size_t)u * kStreamThreads;
-            v[u] = i < n16 ? src[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const f4v* p = reinterpret_cast<const f4v*>(src + i);
+            if (i < n16)
+                v[u] = NT ? __builtin_nontemporal_load(p) : *p;
+            else
+                v[u] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
         }
 #pragma unroll
-        for (int u = 0; u < kStreamLoads; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+        for (int u = 0; u < L; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
     }
     __shared__ float red[kStreamThreads];
     red[threadIdx.x] = acc;
@@ -127,19 +133,34 @@ hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_probe_read(const void* src, size_t bytes, int reps, float* sink,
-                             hipStream_t s) {
+template <int L, bool NT>
+hipError_t launch_probe_read_shape(const void* src, size_t bytes, int reps, float* sink,
+                                   hipStream_t s) {
     const size_t n16 = bytes / 16;
     if (n16 == 0 || reps <= 0) return hipSuccess;
     // chunks * reps work items in all, so each XCD walks the whole buffer
     // reps / 8 times; the grid is a multiple of 8 workgroups (or one work item
     // per workgroup), so work item w always runs on XCD w mod 8.
-    const size_t chunks = (n16 + kStreamChunk16 - 1) / kStreamChunk16;
+    constexpr size_t kChunk16 = (size_t)kStreamThreads * L;
+    const size_t chunks = (n16 + kChunk16 - 1) / kChunk16;
     const size_t items = chunks * (size_t)reps;
     const int blocks = (int)(items < (size_t)kProbeBlocks ? items : (size_t)kProbeBlocks);
-    hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(kStreamThreads), 0, s,
+    hipLaunchKernelGGL((k_probe_read<L, NT>), dim3(blocks), dim3(kStreamThreads), 0, s,
                        reinterpret_cast<const float4*>(src), n16, chunks, items, sink);
     return hipGetLastError();
+}
+
+hipError_t launch_probe_read(const void* src, size_t bytes, int reps, int loads, bool nontemporal,
+                             float* sink, hipStream_t s) {
+    switch (loads * 2 + (nontemporal ? 1 : 0)) {
+        case 8: return launch_probe_read_shape<4, false>(src, bytes, reps, sink, s);
+        case 9: return launch_probe_read_shape<4, true>(src, bytes, reps, sink, s);
+        case 16: return launch_probe_read_shape<8, false>(src, bytes, reps, sink, s);
+        case 17: return launch_probe_read_shape<8, true>(src, bytes, reps, sink, s);
+        case 32: return launch_probe_read_shape<16, false>(src, bytes, reps, sink, s);
+        case 33: return launch_probe_read_shape<16, true>(src, bytes, reps, sink, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace aco

@@ -72,6 +72,8 @@ struct aco_server {
     std::vector<Slot> slots;
     std::vector<SizeClass> classes;
     int max_ants = 0, max_rows = 0;
+    int cus = 0;            // compute units of the device
+    size_t lds_per_cu = 0;  // LDS bytes per compute unit
     hipStream_t init_stream = nullptr;
     bool poisoned = false;
 };
@@ -217,7 +219,8 @@ aco_status aco_server_create(aco_server** out, void* d_pool, size_t pool_bytes, 
     s->classes.resize(num_classes);
     const size_t a = aco::host::kAlign;
     const size_t per = class_table_bytes(max_slots, max_ants, max_rows);
-    hipError_t e = hipStreamCreateWithFlags(&s->init_stream, hipStreamNonBlocking);
+    hipError_t e = aco::host::device_shape(&s->cus, &s->lds_per_cu);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->init_stream, hipStreamNonBlocking);
     for (int c = 0; c < num_classes; ++c) {
         SizeClass& k = s->classes[c];
         char* base = s->pool + (size_t)c * per;
@@ -324,8 +327,11 @@ aco_status aco_server_step(aco_server* s, int32_t* running_out) {
         if (k.dirty) e = rebuild_class(s, (int)c);
         if (e != hipSuccess) return server_fail(s, e, "aco_server_step");
         if (k.running.empty()) continue;
-        e = aco::launch_construct_batch(k.d_cols, k.d_antmap, k.total_ants, k.run_max_n,
-                                        k.stream);
+        e = aco::launch_construct_batch(
+            k.d_cols, k.d_antmap, k.total_ants, k.run_max_n,
+            aco::batch_lds_bytes(k.run_max_n, aco::batch_default_cap(k.total_ants, s->cus),
+                                 s->lds_per_cu),
+            k.stream);
         if (e == hipSuccess) e = aco::launch_best_batch(k.d_cols, (int)k.running.size(), k.stream);
         if (e == hipSuccess)
             e = aco::launch_update_gather_batch(k.d_cols, k.d_rowmap, k.total_rows, k.run_max_ld,

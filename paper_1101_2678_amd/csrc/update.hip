@@ -13,11 +13,19 @@
 //           tour neighbours of city i in every ant's tour), accumulates the
 //           deposits in binary64 LDS slots, then evaporates, adds and
 //           refreshes the choice row.  No global atomics.
-//   atomic  (Section III-B, one thread per city of an ant's tour): each tour
-//           edge adds its deposit with one global binary64 atomic to the
-//           upper-triangle cell of its undirected edge; an epilogue over
-//           pairs of 64 x 64 tiles evaporates, adds the sum to both (i, j)
-//           and (j, i), refreshes the choice matrix and clears the deposits.
+//   atomic  (Section III-B, "atomic instructions + shared memory", the
+//           paper's fastest update): one thread per city of an ant's tour.
+//           The threads of city i (the tours' edges leaving i, read from
+//           succ[i][*]) first add their deposits in binary64 LDS slots keyed
+//           by the edge's other end; each non-zero slot then goes to the
+//           upper-triangle cell of its undirected edge with one global
+//           binary64 atomic, which merges the two directions an edge can be
+//           travelled in.  An epilogue over pairs of 64 x 64 tiles
+//           evaporates, adds the sum to both (i, j) and (j, i), refreshes the
+//           choice matrix and clears the deposits.
+//   atomic_direct (the paper's "atomic instructions" version): the same
+//           epilogue, but every tour edge issues its own global atomic, with
+//           no on-chip combining.
 #include "aco_device.hpp"
 #include "aco_state.hpp"
 #include "nn.hpp"
@@ -146,6 +154,42 @@ __global__ __launch_bounds__(256) void k_deposit_atomic(Colony c) {
     const int i = t[s], j = t[s + 1];
     const int lo = i < j ? i : j, hi = i < j ? j : i;
     unsafeAtomicAdd(&c.delta[(size_t)lo * c.ld + hi], (double)c.dep[k]);
+}
+
+// grid (n, slices): workgroup (i, q) takes the ants k = q, q + slices, ...
+// (interleaved, so every slice reads whole contiguous runs of succ[i][*]).
+// Thread t adds dep_k for the edge i -> succ_k(i) into LDS slot succ_k(i);
+// the non-zero slots then go out as one global atomic each.  An ant's tour
+// holds an undirected edge at most once, so each deposit reaches its cell
+// exactly once, and the binary64 sums stay exact whatever the grouping.
+__global__ __launch_bounds__(kRowThreads) void k_deposit_shared(Colony c) {
+    extern __shared__ double s_D[];  // ld binary64 slots, one per other end j
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < c.ld; j += kRowThreads) s_D[j] = 0.0;
+    __syncthreads();
+    const uint16_t* sr = c.succ + (size_t)i * c.mp;
+    const int step = (int)gridDim.y * kRowThreads;
+    for (int k = (int)blockIdx.y * kRowThreads + tid; k < c.m; k += step)
+        unsafeAtomicAdd(&s_D[sr[k]], (double)c.dep[k]);
+    __syncthreads();
+    for (int j = tid; j < c.n; j += kRowThreads) {
+        const double v = s_D[j];
+        if (v != 0.0) {
+            const int lo = i < j ? i : j, hi = i < j ? j : i;
+            unsafeAtomicAdd(&c.delta[(size_t)lo * c.ld + hi], v);
+        }
+    }
+}
+
+// Ant slices of the shared-memory deposit: enough workgroups to fill the
+// device (about 2048) when there are few rows, never fewer than 256 ants a
+// slice.
+int deposit_slices(int n, int m) {
+    const int by_ants = (m + kRowThreads - 1) / kRowThreads;
+    const int by_rows = (2048 + n - 1) / n;
+    const int s = by_rows < by_ants ? by_rows : by_ants;
+    return s < 1 ? 1 : s;
 }
 
 constexpr int kTile = 64;
@@ -296,9 +340,13 @@ hipError_t launch_update_gather(const Colony& c, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_update_atomic(const Colony& c, hipStream_t s) {
+hipError_t launch_update_atomic(const Colony& c, bool combine_in_lds, hipStream_t s) {
     if (!c.delta) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_deposit_atomic, dim3((c.n + 255) / 256, c.m), dim3(256), 0, s, c);
+    if (combine_in_lds)
+        hipLaunchKernelGGL(k_deposit_shared, dim3(c.n, deposit_slices(c.n, c.m)),
+                           dim3(kRowThreads), (size_t)c.ld * sizeof(double), s, c);
+    else
+        hipLaunchKernelGGL(k_deposit_atomic, dim3((c.n + 255) / 256, c.m), dim3(256), 0, s, c);
     const int nt = c.ld / kTile;
     hipLaunchKernelGGL(k_update_epilogue, dim3(nt, nt), dim3(256), 0, s, c);
     return hipGetLastError();

@@ -168,13 +168,35 @@ def make_requests(count: int, rate_per_s: float, n_lo: int = 100, n_hi: int = 30
     return reqs
 
 
-def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: float = 1e-4):
-    """Replays the arrival trace in real time: arrivals join a FIFO queue, the
-    head is admitted as soon as the server accepts it, the server is polled
-    (each size class ticks on its own), and finished requests are read and
-    released."""
+def admission_order(queue, now: float, age_bound_s: float):
+    """The order in which waiting requests are offered to the server: those
+    that have waited longer than `age_bound_s` first, oldest first (no
+    request is passed over for longer than that), then the rest by the work
+    they ask for (iterations x m x n^2, the construction reads of a solve),
+    smallest first, arrival breaking ties."""
+    aged = [r for r in queue if now - r.arrival > age_bound_s]
+    young = [r for r in queue if now - r.arrival <= age_bound_s]
+    aged.sort(key=lambda r: (r.arrival, r.rid))
+    young.sort(key=lambda r: (r.iters * r.m * r.n * r.n, r.arrival, r.rid))
+    return aged + young
+
+
+def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: float = 1e-4,
+                  policy: str = "size", age_bound_s: float = 10.0):
+    """Replays the arrival trace in real time.  Arrivals join a queue; at every
+    poll the waiting requests are offered to the server, and each one it
+    accepts (a slot, class capacity and pool memory are free) is admitted.
+    policy "size": offered in admission_order (small solves first, with an
+    aging bound, so that small requests are not held behind large ones);
+    policy "fifo": strictly in arrival order, stopping at the first refusal.
+    A request that has waited beyond the aging bound and is refused stops the
+    offers behind it, so the capacity it waits for is not taken by others.
+    The server is polled (each size class ticks on its own), and finished
+    requests are read and released."""
+    if policy not in ("size", "fifo"):
+        raise ValueError(f"unknown admission policy {policy!r}")
     pending = deque(sorted(requests, key=lambda r: r.arrival))
-    queue: deque = deque()
+    queue: list = []
     slot_req = {}
     by_id = {r.rid: r for r in requests}
     done = 0
@@ -184,16 +206,26 @@ def run_open_loop(server: Server, requests, keep_tau: bool = False, idle_sleep: 
         now = time.perf_counter() - t0
         while pending and pending[0].arrival <= now:
             queue.append(pending.popleft())
-        while queue:
-            slot = server.submit(queue[0])
-            if slot is None:
-                if not slot_req:
-                    raise RuntimeError(f"request {queue[0].rid} (n={queue[0].n}) can never be "
-                                       "admitted: pool, slots or class capacity too small")
-                break
-            r = queue.popleft()
-            r.admitted = time.perf_counter() - t0
-            slot_req[slot] = r
+        if queue and len(slot_req) < server.max_slots:
+            offers = queue if policy == "fifo" else admission_order(queue, now, age_bound_s)
+            admitted = []
+            for r in offers:
+                if len(slot_req) >= server.max_slots:
+                    break
+                slot = server.submit(r)
+                if slot is None:
+                    if not slot_req:
+                        raise RuntimeError(f"request {r.rid} (n={r.n}) can never be admitted: "
+                                           "pool, slots or class capacity too small")
+                    if policy == "fifo" or now - r.arrival > age_bound_s:
+                        break
+                    continue
+                r.admitted = time.perf_counter() - t0
+                slot_req[slot] = r
+                admitted.append(r)
+            if admitted:
+                gone = {r.rid for r in admitted}
+                queue = [r for r in queue if r.rid not in gone]
         running = server.step()
         peak = max(peak, running)
         finished = server.collect()
@@ -235,10 +267,20 @@ def run_plain(requests, device="cuda"):
     return summarize(requests, 1)
 
 
+SIZE_CLASSES = ((100, 512), (513, 1024), (1025, 2048), (2049, 4096))
+
+
 def summarize(requests, peak_running: int) -> dict:
     lat = np.array([r.finished - r.arrival for r in requests])
     first = min(r.arrival for r in requests)
     last = max(r.finished for r in requests)
+    per_class = {}
+    for lo, hi in SIZE_CLASSES:
+        sel = np.array([lo <= r.n <= hi for r in requests])
+        if sel.any():
+            per_class[f"n{lo}-{hi}"] = {"requests": int(sel.sum()),
+                                        "latency_p50_s": round(float(np.percentile(lat[sel], 50)), 4),
+                                        "latency_p99_s": round(float(np.percentile(lat[sel], 99)), 4)}
     return {
         "requests": len(requests),
         "solves_per_s": len(requests) / (last - first),
@@ -248,4 +290,5 @@ def summarize(requests, peak_running: int) -> dict:
         "latency_max_s": float(lat.max()),
         "makespan_s": last - first,
         "peak_running": peak_running,
+        "by_size": per_class,
     }

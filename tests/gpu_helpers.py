@@ -48,7 +48,7 @@ def compare_run(dist, m, alpha, beta, rho, seed, iters, kinds=("gather", "atomic
     log(f"  parity n={n} m={m} alpha={alpha} beta={beta} rho={rho} seed={seed} iters={iters} "
         f"nn={nn} rule={rule}")
     ref = oracle.init(dist, m, alpha, beta, rho, seed)
-    cols = {k: Colony(dist, m, alpha, beta, rho, seed, atomic=(k == "atomic")) for k in kinds}
+    cols = {k: Colony(dist, m, alpha, beta, rho, seed, atomic=(k != "gather")) for k in kinds}
     nnl = None
     if nn is not None:
         nnl = oracle.nn_lists(dist, nn)

@@ -33,8 +33,10 @@ def test_update_byte_models_hand_count(bench):
     n, m = 10, 4
     # gather: tau r/w, dist r, choice w (16 n^2), succ/pred rows (4 m n), deposits (4 m)
     assert bench.gather_bytes(n, m) == 16 * 100 + 4 * 40 + 16
-    # atomic: tours (2 m (n + 1)), deposits (4 m), m n atomics of 16 B, epilogue 24 n^2
+    # direct atomic: tours (2 m (n + 1)), deposits (4 m), m n atomics of 16 B, epilogue 24 n^2
     assert bench.atomic_bytes(n, m) == 2 * 4 * 11 + 16 + 16 * 40 + 24 * 100
+    # shared-memory atomic: successor table (2 m n), deposits (4 m), epilogue 24 n^2
+    assert bench.atomic_shared_bytes(n, m) == 2 * 40 + 16 + 24 * 100
 
 
 def test_job_roofline_record(bench):
@@ -61,3 +63,16 @@ def test_more_than_one_gpu_is_refused():
     assert out.returncode == 2
     rec = json.loads(out.stdout.strip().splitlines()[-1])
     assert "one GPU" in rec["error"]
+
+
+def test_requested_bytes_hand_count(bench):
+    import numpy as np
+
+    # n = 8, tour 0..7: group {0..3} is last needed at step 3, group {4..7}
+    # at step 7, so the skip path loads 3 + 7 sixteen-byte groups
+    t = np.array([[0, 1, 2, 3, 4, 5, 6, 7, 0]], np.uint16)
+    assert bench.requested_bytes(t, 8, skip=True) == 16 * (3 + 7)
+    assert bench.requested_bytes(t, 8, skip=False) == 16 * 2 * 7
+    # n = 6 (groups {0..3}, {4, 5}): tour 5 0 4 1 2 3 -> last positions 5 and 2
+    t = np.array([[5, 0, 4, 1, 2, 3, 5]], np.uint16)
+    assert bench.requested_bytes(t, 6, skip=True) == 16 * (5 + 2)

@@ -243,3 +243,58 @@ def test_autotune_sets_table_and_keeps_results():
         compare_run(d, 80, 1, 2, 0.5, 9, 2, kinds=("gather",))
     finally:
         aco.reset_tiles()
+
+
+def test_batch_configs_same_bits():
+    """The batched launch configuration (per-CU workgroup cap, tile per size)
+    changes speed only: from a fresh batch, every candidate configuration
+    gives the tours, lengths, tau and best tour of the default one, bit for
+    bit, over 3 iterations; the autotuner keeps one of the candidates and the
+    batch goes on computing exactly what a fresh batch computes."""
+    from paper_1101_2678_amd import aco
+
+    dists, params = _batch_case()
+    ref = aco.Batch(dists, params)
+    ref.run(3, graph=False)
+    ref.sync()
+    want = [(ref.tours(q), ref.tau(q), ref.best(q)) for q in range(len(dists))]
+    ref.close()
+    cands = [(0, -1), (3, -1), (8, 0), (16, 1024), (24, 256), (64, 0)]
+    for cfg in cands:
+        log(f"  batch config wg_per_cu={cfg[0]} tile4_max_n={cfg[1]}")
+        b = aco.Batch(dists, params)
+        b.set_config(*cfg)
+        assert b.config == {"wg_per_cu": cfg[0], "tile4_max_n": cfg[1]}
+        b.run(3, graph=True)
+        b.sync()
+        for q in range(len(dists)):
+            (wt, wl), wtau, (wbt, wbl) = want[q]
+            gt, gl = b.tours(q)
+            assert (gt == wt).all() and (gl == wl).all(), f"config {cfg}: instance {q} tours"
+            assert_same_f32(b.tau(q), wtau, f"config {cfg}: instance {q} tau")
+            bt, bl = b.best(q)
+            assert bl == wbl and (bt == wbt).all()
+        b.close()
+    # the autotuner: 6 candidates x (1 + 1) iterations, then 2 more iterations,
+    # against a fresh batch run for the same 14 iterations
+    b = aco.Batch(dists, params)
+    best, ms = b.autotune(cands, iters=1)
+    assert 0 <= best < len(cands) and (ms > 0).all()
+    assert b.config == {"wg_per_cu": cands[best][0], "tile4_max_n": cands[best][1]}
+    b.run(2, graph=True)
+    b.sync()
+    fresh = aco.Batch(dists, params)
+    fresh.run(14, graph=False)
+    fresh.sync()
+    for q in range(len(dists)):
+        assert b.iteration(q) == 14
+        assert_same_f32(b.tau(q), fresh.tau(q), f"autotuned batch: instance {q} tau")
+        assert b.best(q)[1] == fresh.best(q)[1]
+    with pytest.raises(aco.AcoError) as e:
+        b.set_config(65, -1)
+    assert e.value.status == aco.ACO_ERR_INVALID
+    with pytest.raises(aco.AcoError) as e:
+        b.set_config(0, 1025)
+    assert e.value.status == aco.ACO_ERR_INVALID
+    b.close()
+    fresh.close()

@@ -103,7 +103,7 @@ def test_parity_config_n100():
     """n = m = 100, uniform in [0, 10^4]^2, alpha 1, beta 2, rho 0.5, seed 1,
     10 iterations: every tour, length, tau and choice bit-exact."""
     _, d = tsp_inputs.instance(100, "uniform", side=10_000, seed=1)
-    compare_run(d, 100, 1, 2, 0.5, 1, 10)
+    compare_run(d, 100, 1, 2, 0.5, 1, 10, kinds=("gather", "atomic", "atomic_direct"))
 
 
 @pytest.mark.parametrize("n,m,alpha,beta,rho", [
@@ -113,7 +113,8 @@ def test_parity_config_n100():
 ])
 def test_parity_ragged(n, m, alpha, beta, rho):
     _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=n)
-    compare_run(d, m, alpha, beta, rho, seed=n + 7, iters=3)
+    compare_run(d, m, alpha, beta, rho, seed=n + 7, iters=3,
+                kinds=("gather", "atomic", "atomic_direct"))
 
 
 @pytest.mark.parametrize("n", [1025, 1536, 1537, 2048])
@@ -133,7 +134,7 @@ def test_parity_n1000_full(layout):
     with the gather and the atomic update, in the launch configuration the
     benchmark times."""
     _, d = tsp_inputs.instance(1000, layout, side=1_000_000, seed=1)
-    compare_run(d, 1000, 1, 2, 0.5, 1, 20)
+    compare_run(d, 1000, 1, 2, 0.5, 1, 20, kinds=("gather", "atomic", "atomic_direct"))
 
 
 def test_subnormal_choice_values():
@@ -170,11 +171,14 @@ def test_n2400_invariants_after_convergence():
     _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=1)
     g = Colony(d, m, 1, 2, 0.5, 1, atomic=True)
     a = Colony(d, m, 1, 2, 0.5, 1, atomic=True)
+    x = Colony(d, m, 1, 2, 0.5, 1, atomic=True)
     for it in range(10):
         g.construct(it)
         g.update("gather")
         a.construct(it)
         a.update("atomic")
+        x.construct(it)
+        x.update("atomic_direct")
     for it in range(10, 13):
         log(f"  n=2400 iteration {it}")
         tau_before = g.tau()
@@ -186,10 +190,13 @@ def test_n2400_invariants_after_convergence():
         assert (np.sort(gt[:, :-1], axis=1) == np.arange(n)).all(), "not a permutation"
         assert (gt[:, 0] == gt[:, -1]).all()
         assert all(tour_length(d, gt[k]) == gl[k] for k in range(m))
+        x.construct(it)
         g.update("gather")
         a.update("atomic")
+        x.update("atomic_direct")
         tg, ta = g.tau(), a.tau()
         assert_same_f32(tg, ta, f"it={it} gather vs atomic tau")
+        assert_same_f32(x.tau(), ta, f"it={it} atomic_direct vs atomic tau")
         assert (tg.view(np.uint32) == tg.T.view(np.uint32)).all()
         untouched = np.ones((n, n), bool)
         idx = gt[:, :-1].astype(np.int64), gt[:, 1:].astype(np.int64)
@@ -198,6 +205,7 @@ def test_n2400_invariants_after_convergence():
         assert (tg[untouched] == tau_before[untouched] * np.float32(0.5)).all()
     g.close()
     a.close()
+    x.close()
 
 
 def test_restore_resumes_bit_exact_and_validates():
@@ -301,6 +309,8 @@ def test_max_cities_sampled(rule):
 
 def test_max_ants():
     """m = 65535 ants, the largest colony (one workgroup per ant, the top of
-    the 16-bit ant field): every tour, length and tau bit-exact, both updates."""
+    the 16-bit ant field): every tour, length and tau bit-exact, all three
+    updates (the shared-memory deposit splits the ants of a row over 128
+    workgroups here)."""
     _, d = tsp_inputs.instance(16, "uniform", side=10_000, seed=65535)
-    compare_run(d, 65535, 1, 2, 0.5, 7, iters=2)
+    compare_run(d, 65535, 1, 2, 0.5, 7, iters=2, kinds=("gather", "atomic", "atomic_direct"))
