@@ -856,13 +856,21 @@ def main():
     if args.workload == "served":
         print(json.dumps(bench_served(args, torch, aco)), flush=True)
         return
-    if args.workload != "all":
+    if args.workload not in ("all", "n2400"):
         rec, _ = run_single(args, torch, aco, args.workload, args.steps, args.warmup, main=False)
         print(json.dumps(rec), flush=True)
         return
 
     rec, d = run_single(args, torch, aco, "n2400", args.steps, args.warmup, main=True)
     n, m = rec["config"]["n"], rec["config"]["m"]
+    # a plain copy of known size: profiled runs calibrate FETCH_SIZE and
+    # WRITE_SIZE on it
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    aco.probe_copy(dst, src)
+    torch.cuda.synchronize()
+    rec["copy_calibration_bytes"] = src.numel() * 4
+    del src, dst
     if not args.no_probe:
         log("bench: HBM and 160 MB streaming probes, random-row probes")
         rec["probe"] = {
@@ -881,6 +889,29 @@ def main():
         log(f"bench: candidate-list construction, nn={args.nn}")
         rec["nn_list"] = bench_nn(torch, aco, d, m, args.nn, args.steps, args.warmup,
                                   args.update, min(3.0, args.cpu_seconds))
+    if args.workload == "all":
+        configs = rec["configs"] = run_configs(args, torch, aco)
+        srv = configs["served"]
+        rec["served_solves_per_s"] = srv["value"]
+        rec["served_latency_p50_s"] = srv["latency_p50_s"]
+        rec["served_latency_p99_s"] = srv["latency_p99_s"]
+        rec["served_plain_solves_per_s"] = round(
+            srv["plain_one_request_at_a_time"]["solves_per_s"], 3)
+        rec["served_plain_latency_p99_s"] = round(
+            srv["plain_one_request_at_a_time"]["latency_p99_s"], 4)
+        rec["batch256_solves_per_s"] = configs["batch256"]["value"]
+        rec["batch256_one_per_launch_solves_per_s"] = (
+            configs["batch256"]["one_instance_per_launch"]["solves_per_s"])
+    if args.cpu_seconds > 0:
+        log(f"bench: timing the oracle (up to ~{args.cpu_seconds:.0f} s of host work)")
+        rec["cpu_baseline"] = cpu_baseline(d, m, args.cpu_seconds)
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+
+
+def run_configs(args, torch, aco) -> dict:
+    """Every workload other than n = 2400, as sub-records of the main line."""
     configs = {}
     for name in ("n100", "n1000u", "n1000c"):
         configs[name], _ = run_single(args, torch, aco, name, args.steps, args.warmup,
@@ -889,23 +920,7 @@ def main():
     configs["batch256"] = bench_batch(args, torch, aco)
     log("bench: served")
     configs["served"] = bench_served(args, torch, aco)
-    rec["configs"] = configs
-    srv = configs["served"]
-    rec["served_solves_per_s"] = srv["value"]
-    rec["served_latency_p50_s"] = srv["latency_p50_s"]
-    rec["served_latency_p99_s"] = srv["latency_p99_s"]
-    rec["served_plain_solves_per_s"] = round(srv["plain_one_request_at_a_time"]["solves_per_s"], 3)
-    rec["served_plain_latency_p99_s"] = round(
-        srv["plain_one_request_at_a_time"]["latency_p99_s"], 4)
-    rec["batch256_solves_per_s"] = configs["batch256"]["value"]
-    rec["batch256_one_per_launch_solves_per_s"] = (
-        configs["batch256"]["one_instance_per_launch"]["solves_per_s"])
-    if args.cpu_seconds > 0:
-        log(f"bench: timing the oracle (up to ~{args.cpu_seconds:.0f} s of host work)")
-        rec["cpu_baseline"] = cpu_baseline(d, m, args.cpu_seconds)
-    else:
-        rec["cpu_baseline"] = None
-    print(json.dumps(rec), flush=True)
+    return configs
 
 
 if __name__ == "__main__":
