@@ -63,7 +63,8 @@ __device__ __forceinline__ uint64_t initial_lane_bits(int n, int lane) {
     return bits;
 }
 
-// s_vis[b]: bit t set <=> city 64b + t is visited or does not exist.
+// Visited bits of block b, kept in lane b of a register pair: bit t set <=>
+// city 64b + t is visited or does not exist.
 __device__ __forceinline__ uint64_t initial_block_bits(int n, int b) {
     const int valid = n - 64 * b;
     if (valid <= 0) return ~0ull;
@@ -71,13 +72,18 @@ __device__ __forceinline__ uint64_t initial_block_bits(int n, int b) {
     return ~0ull << valid;
 }
 
-// Clears city j in both tabu representations (called with j uniform).
+// The value lane l holds in v, on every lane (l wave-uniform).
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Marks city j visited in both tabu representations (called with j uniform).
 template <int G>
 __device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& lane_bits,
-                                             uint64_t* s_vis) {
-    if (lane == 0)
-        __hip_atomic_fetch_or(&s_vis[j >> 6], 1ull << (j & 63), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                                             uint64_t& block_bits) {
+    if (lane == (j >> 6)) block_bits |= 1ull << (j & 63);
     const int owner = (j % Tile<G>::kPass) / G;
     const int bit = (j / Tile<G>::kPass) * G + (j % G);
     if (lane == owner) lane_bits &= ~(1ull << bit);
@@ -174,19 +180,25 @@ __device__ __forceinline__ void load_row(const float* __restrict__ row, int n, i
     }
 }
 
+// Rows of at most 1024 cities: after masking, every pass's weights go to LDS
+// (s_w, city c at s_w[c]), so a candidate block is read back with one load
+// and nothing is staged on the way to the selection.  Longer rows keep the
+// masked weights in registers and stage only the pass of a candidate block.
+template <int G, int P>
+constexpr bool kWriteAllPasses = (P * Tile<G>::kPass <= 1024);
+
 // One R64 roulette draw over a loaded row (wa/wb as load_row leaves them;
 // masked in place), with np <= P passes in use (np == P when GUARD is
-// false).  Returns the chosen city, or -1 if no city is feasible.
-// Wave-uniform.  The masked weights stay in registers; the pass holding a
-// candidate block is staged into LDS only when that block is scanned.  The
-// workgroup is one wavefront: its LDS operations execute in program order,
-// and every LDS access below uses a lane-dependent index, so the compiler
-// keeps the order.
+// false).  block_bits: the visited bits of block b in lane b.  Returns the
+// chosen city, or -1 if no city is feasible.  Wave-uniform.  The workgroup is
+// one wavefront: its LDS operations execute in program order, and every LDS
+// access below uses a lane-dependent index, so the compiler keeps the order.
 template <int G, int P, bool GUARD>
 __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n, int np,
-                                           uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
+                                           uint64_t lane_bits, uint64_t block_bits, float* s_T,
                                            float* s_w, float u, int lane) {
     constexpr int LPB = Tile<G>::kLanesPerBlock;
+    constexpr bool kAll = kWriteAllPasses<G, P>;
     const int nb = (n + 63) >> 6;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -199,6 +211,11 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
             t = pair_sum4(wa[p]) + pair_sum4(wb[p]);
         } else {
             t = pair_sum4(wa[p]);
+        }
+        if (kAll) {
+            u32x4* dst = reinterpret_cast<u32x4*>(s_w + p * Tile<G>::kPass + lane * G);
+            dst[0] = wa[p];
+            if (G == 8) dst[1] = wb[p];
         }
         t = group_pairwise<LPB>(t);
         if ((lane % LPB) == LPB - 1) s_T[p * G + lane / LPB] = t;
@@ -213,29 +230,33 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
     while (cand) {
         const int b = __builtin_ctzll(cand);
         cand &= cand - 1;
-        stage_block<G, P>(wa, wb, b, s_w, lane);
-        const uint64_t vis = s_vis[b];
-        const float w = s_w[(b % G) * 64 + lane];
-        const bool feasible = ((vis >> lane) & 1ull) == 0ull;
+        float w;
+        if (kAll) {
+            w = s_w[b * 64 + lane];
+        } else {
+            stage_block<G, P>(wa, wb, b, s_w, lane);
+            w = s_w[(b % G) * 64 + lane];
+        }
+        const uint64_t vis = lane_u64(block_bits, b);
         const float s = s64_scan(w);
         const float eb = read_lane(E, b);
-        const uint64_t hit = ballot(feasible && (eb + s) > target);
+        const uint64_t hit = ballot((eb + s) > target) & ~vis;
         if (hit) return b * 64 + __builtin_ctzll(hit);
     }
     // No prefix exceeds the target: the highest feasible city.
-    const uint64_t live = ballot(~s_vis[lane] != 0ull);
+    const uint64_t live = ballot(~block_bits != 0ull);
     if (!live) return -1;
     const int b = 63 - __builtin_clzll(live);
-    return b * 64 + 63 - __builtin_clzll(~s_vis[b]);
+    return b * 64 + 63 - __builtin_clzll(~lane_u64(block_bits, b));
 }
 
 template <int G, int P, bool GUARD, bool SKIP>
 __device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
-                                        uint64_t lane_bits, const uint64_t* s_vis, float* s_T,
+                                        uint64_t lane_bits, uint64_t block_bits, float* s_T,
                                         float* s_w, float u, int lane) {
     u32x4 wa[P], wb[P];
     load_row<G, P, GUARD, SKIP>(row, n, np, lane_bits, lane, wa, wb);
-    return pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, s_vis, s_T, s_w, u, lane);
+    return pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, block_bits, s_T, s_w, u, lane);
 }
 
 // Uniform draws for steps s0 .. s0+63: lane t holds u of step s0 + t.  The
@@ -248,8 +269,7 @@ __device__ __forceinline__ float draws64(PhiloxKey key, uint32_t iter, uint32_t 
 
 // LDS a construction workgroup needs besides the tour.
 struct AntShared {
-    float w[512];       // staged candidate block weights (64 G floats)
-    uint64_t vis[64];   // visited bits per 64-city block
+    float w[1024];      // masked weights of rows up to 1024 cities, else a staged pass
     float T[64];        // block totals in block order
 };
 
@@ -263,7 +283,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     const int np = GUARD ? (n + Tile<G>::kPass - 1) / Tile<G>::kPass : P;
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
-    sh.vis[lane] = initial_block_bits(n, lane);
+    uint64_t block_bits = initial_block_bits(n, lane);
     sh.T[lane] = 0.0f;
     uint64_t lane_bits = initial_lane_bits<G, P>(n, lane);
     __syncthreads();
@@ -271,7 +291,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
     if (lane == 0) s_tour[0] = (uint16_t)cur;
-    mark_visited<G>(cur, lane, lane_bits, sh.vis);
+    mark_visited<G>(cur, lane, lane_bits, block_bits);
 
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
@@ -279,12 +299,13 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
         if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const float* row = c.choice + (size_t)cur * c.ld;
-        int j = r64_pick<G, P, GUARD, SKIP>(row, n, np, lane_bits, sh.vis, sh.T, sh.w, u, lane);
+        int j = r64_pick<G, P, GUARD, SKIP>(row, n, np, lane_bits, block_bits, sh.T, sh.w, u,
+                                            lane);
         // At every step n - step >= 1 cities are unvisited, so j >= 0; the
         // clamp only keeps the LDS indices in range should that ever break.
         j = j < 0 ? 0 : j;
         if (lane == 0) s_tour[step] = (uint16_t)j;
-        mark_visited<G>(j, lane, lane_bits, sh.vis);
+        mark_visited<G>(j, lane, lane_bits, block_bits);
         cur = j;
     }
     __syncthreads();
@@ -357,7 +378,6 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
         const int j = lane * 64 + t;
         if (j < n && f[j]) vis &= ~(1ull << t);
     }
-    sh.vis[lane] = vis;
     sh.T[lane] = 0.0f;
     uint64_t lane_bits = 0;
 #pragma unroll
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
             if (j < n && f[j]) lane_bits |= 1ull << (p * G + e);
         }
     __syncthreads();
-    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, n, P, lane_bits, sh.vis, sh.T,
+    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, n, P, lane_bits, vis, sh.T,
                                               sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
