@@ -83,6 +83,17 @@ __device__ __forceinline__ float s64_scan(float x) {
     return x;
 }
 
+// Stage A of S64 alone: the inclusive prefix of lanes 0..15 (row 0), which
+// stage B leaves as it is.  Equal to s64_scan on lanes 0..15; the other rows
+// hold their own row prefixes.
+__device__ __forceinline__ float s64_scan_row0(float x) {
+    x = x + dpp_move<0x111, 0xF>(x);
+    x = x + dpp_move<0x112, 0xF>(x);
+    x = x + dpp_move<0x114, 0xF>(x);
+    x = x + dpp_move<0x118, 0xF>(x);
+    return x;
+}
+
 // Lane l receives lane l-1's value, lane 0 receives +0.
 __device__ __forceinline__ float wave_shift_up1(float x) { return dpp_move<0x138, 0xF>(x); }
 

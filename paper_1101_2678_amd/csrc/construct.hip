@@ -220,13 +220,15 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
         t = group_pairwise<LPB>(t);
         if ((lane % LPB) == LPB - 1) s_T[p * G + lane / LPB] = t;
     }
+    // Rows of at most 1024 cities have nb <= 16 blocks, all in row 0 of the
+    // block-total scan, which stage B leaves as it is.
     const float T = s_T[lane];
-    const float I = s64_scan(T);
+    const float I = kAll ? s64_scan_row0(T) : s64_scan(T);
     const float total = read_lane(I, nb - 1);
     const float target = u * total;
     const float E = wave_shift_up1(I);
     const float bound = E + T * kBlockSlack;
-    uint64_t cand = ballot(lane < nb && bound > target);
+    uint64_t cand = ballot(bound > target) & (nb >= 64 ? ~0ull : (1ull << nb) - 1ull);
     while (cand) {
         const int b = __builtin_ctzll(cand);
         cand &= cand - 1;
