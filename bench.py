@@ -55,8 +55,8 @@ WORKLOADS = {
 }
 ALPHA, BETA, RHO = 1, 2, 0.5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "construct_n2400_traffic.json")
-KERNEL_SOURCES = ["paper_1101_2678_amd/csrc/construct.hip", "paper_1101_2678_amd/csrc/aco_device.hpp",
-                  "paper_1101_2678_amd/csrc/aco_state.hpp"]
+KERNEL_SOURCES = ["paper_1101_2678_amd/csrc/construct.hip", "paper_1101_2678_amd/csrc/r64_lanes.hpp",
+                  "paper_1101_2678_amd/csrc/aco_device.hpp", "paper_1101_2678_amd/csrc/aco_state.hpp"]
 
 
 def log(msg):
@@ -531,9 +531,10 @@ def bench_batch(args, torch, aco):
              for q, n in enumerate(sizes)]
     params = [dict(m=int(n), alpha=ALPHA, beta=BETA, rho=RHO, seed=q + 1)
               for q, n in enumerate(sizes)]
-    chosen, ms4, ms8 = aco.autotune([64, 128, 256, 512, 1024], reps=3)
-    log(f"bench batch: autotune chosen tiles {chosen.tolist()} (ms tile4 {ms4.tolist()}, "
-        f"tile8 {ms8.tolist()})")
+    tune_sizes = [64, 128, 256, 512, 1024]
+    tiles, waves, shape_ms = aco.autotune(tune_sizes, reps=3)
+    log(f"bench batch: autotune chose tiles {tiles.tolist()} waves {waves.tolist()} "
+        f"(ms per shape {aco.SHAPES}: {np.round(shape_ms, 4).tolist()})")
     stream = torch.cuda.Stream()
     b = aco.Batch(dists, params, stream=stream)
     default_cfg = b.config
@@ -586,7 +587,13 @@ def bench_batch(args, torch, aco):
                                     "solves_per_s": round(count / t_single, 2)},
         "speedup_vs_one_per_launch": round(t_single / t_batch, 2),
         "ant_steps_per_s": round(ant_steps / t_batch, 1),
-        "tiles": {"sizes": [64, 128, 256, 512, 1024], "chosen": chosen.tolist()},
+        "shapes": {"sizes": tune_sizes, "tile": tiles.tolist(), "waves": waves.tolist(),
+                   "ms_per_construction": {f"tile{t}_waves{w}": [round(float(x), 4) for x in col]
+                                           for (t, w), col in zip(aco.SHAPES, shape_ms.T)},
+                   "note": "single-instance construction shape per size (m = n) from the "
+                           "autotuner, used by the one-instance-per-launch comparison; the "
+                           "batched launch takes only the tile; -1 = shape does not support "
+                           "the size"},
         "launch_autotune": {
             "candidates": [{"wg_per_cu": w, "tile4_max_n": t, "ms_per_iteration": round(float(x), 4)}
                            for (w, t), x in zip(cands, cand_ms)],

@@ -272,6 +272,14 @@ aco_status aco_test_select(int32_t tile, int32_t n, int32_t count, const float* 
                            const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
                            void* hip_stream);
 
+/* As aco_test_select, through the construction kernel of the given shape:
+ * `waves` wavefronts per ant share the row (1, or 2 / 4 where
+ * aco_set_shape accepts the shape for n).  The result must not depend on
+ * tile or waves.  Asynchronous on hip_stream. */
+aco_status aco_test_select_shape(int32_t tile, int32_t waves, int32_t n, int32_t count,
+                                 const float* rows_dev, const uint8_t* feasible_dev,
+                                 const float* u_dev, int32_t* out_dev, void* hip_stream);
+
 /* The product selection on `count` independent rows through the device code
  * aco_construct_product uses, with the draws given instead of generated.
  *   rows_dev      count rows of ld floats (device), ld = n rounded up to 64,
@@ -284,32 +292,53 @@ aco_status aco_test_product_select(int32_t n, int32_t count, const float* rows_d
                                    const uint8_t* feasible_dev, const float* u_dev,
                                    int32_t* out_dev, void* hip_stream);
 
-/* ---- construction tiles ------------------------------------------------ */
+/* ---- construction shapes ----------------------------------------------- */
 
-/* The construction kernel spreads a choice row over a wavefront with
- * `cities_per_lane` (4 or 8) consecutive cities per lane per pass (the
- * paper's city tiling, Section III-A).  The tile changes speed only, never
- * results.  aco_set_tile sets the tile for instance sizes n_lo..n_hi (tile 4
- * only for n <= 1024); contexts and batches created afterwards use it.  The
- * table is process-wide and not thread-safe.  Default: 4 for n <= 256, 8
- * above (the faster tile of each size for single-instance construction with
- * m = n on MI355X). */
+/* The construction kernel spreads a choice row over the threads of an ant's
+ * workgroup (the paper's city tiling and thread blocks, Section III-A):
+ * `cities_per_lane` (4 or 8) consecutive cities per lane per pass of
+ * 64 * cities_per_lane cities, and `waves_per_ant` wavefronts per ant that
+ * share the passes (wave w takes passes w, w + W, ...).  The shape changes
+ * speed only, never results.  Supported shapes:
+ *   1 wavefront:  tile 8 for any n; tile 4 for n <= 1024;
+ *   2 wavefronts: n <= 1024 with at least 2 passes (tile 8: n >= 513;
+ *                 tile 4: n >= 257);
+ *   4 wavefronts: tile 4 with 4 passes (769 <= n <= 1024).
+ * aco_set_shape sets the shape for instance sizes n_lo..n_hi and fails if
+ * any size of the range does not support it; aco_set_tile(lo, hi, t) is
+ * aco_set_shape(lo, hi, t, 1).  Contexts created afterwards use the table
+ * (batched construction always runs one wavefront per ant and takes only the
+ * tile).  The table is process-wide and not thread-safe.  Default: tile 4
+ * for n <= 256, 8 above, one wavefront per ant. */
+aco_status aco_set_shape(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane,
+                         int32_t waves_per_ant);
 aco_status aco_set_tile(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane);
 int32_t aco_get_tile(int32_t n);
-/* Restores the default table (above).  Same thread-safety as aco_set_tile. */
+int32_t aco_get_waves(int32_t n);
+/* Restores the default table (above).  Same thread-safety as aco_set_shape. */
 void aco_reset_tiles(void);
+
+/* The shapes the autotuner times, as (cities per lane, wavefronts per ant),
+ * in the order of its ms columns: 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
+ * 3 = (4, 2), 4 = (4, 4). */
+#define ACO_NUM_SHAPES 5
 
 /* Autotuner: for each of the `count` strictly increasing instance sizes
  * (3..4096), builds a synthetic uniform instance with m = n on d_workspace
  * (>= aco_workspace_bytes for the largest size with m = n, without the
- * atomic part), times `reps` constructions with every supported tile, and
- * sets the tile table so that bucket i, sizes (sizes[i-1], sizes[i]] (the
- * last bucket up to 4096), uses the fastest tile.  chosen (count int32),
- * ms_tile4 and ms_tile8 (count floats, -1 where unsupported) may be NULL.
- * Synchronous; overwrites the workspace. */
+ * atomic part), times `reps` constructions with every shape that supports
+ * the size, and sets the shape table so that bucket i, sizes
+ * (sizes[i-1], sizes[i]] (the last bucket up to 4096), uses the fastest;
+ * sizes of the bucket that shape does not support get its tile with one
+ * wavefront (tile 8 where tile 4 stops).
+ *   chosen_tile, chosen_waves  count int32 each: the shape picked per size
+ *   ms                         count * ACO_NUM_SHAPES floats, row i for
+ *                              sizes[i]: ms per construction, -1 where the
+ *                              shape does not support the size
+ * Each output may be NULL.  Synchronous; overwrites the workspace. */
 aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes, int32_t count,
-                        int32_t reps, void* hip_stream, int32_t* chosen, float* ms_tile4,
-                        float* ms_tile8);
+                        int32_t reps, void* hip_stream, int32_t* chosen_tile,
+                        int32_t* chosen_waves, float* ms);
 
 /* ---- batches: many independent instances advanced together --------------- */
 

@@ -23,7 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libaco.so")
-SOURCES = ["construct.hip", "construct_nn.hip", "construct_product.hip", "update.hip", "probe.hip", "aco_abi.hip", "batch.hip", "server.hip", "noalloc.hip"]
+SOURCES = ["construct.hip", "construct_split.hip", "construct_nn.hip", "construct_product.hip", "update.hip", "probe.hip", "aco_abi.hip", "batch.hip", "server.hip", "noalloc.hip"]
 ARCH = os.environ.get("ACO_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

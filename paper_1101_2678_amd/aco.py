@@ -78,8 +78,11 @@ def _load():
         "aco_last_error": (c.c_char_p, []),
         "aco_describe": (i32, [vp, c.c_char_p, sz]),
         "aco_test_select": (i32, [i32, i32, i32, vp, vp, vp, vp, vp]),
+        "aco_test_select_shape": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp]),
         "aco_set_tile": (i32, [i32, i32, i32]),
+        "aco_set_shape": (i32, [i32, i32, i32, i32]),
         "aco_get_tile": (i32, [i32]),
+        "aco_get_waves": (i32, [i32]),
         "aco_reset_tiles": (None, []),
         "aco_autotune": (i32, [vp, sz, vp, i32, i32, vp, vp, vp, vp]),
         "aco_batch_workspace_bytes": (sz, [i32, vp]),
@@ -294,8 +297,9 @@ class Colony:
             pass
 
 
-def test_select(rows, feasible, u, tile: int = 8, stream=None):
-    """R64 roulette on independent rows through the construction kernel's code.
+def test_select(rows, feasible, u, tile: int = 8, waves: int = 1, stream=None):
+    """R64 roulette on independent rows through the construction kernel's code
+    of the given shape (tile cities per lane, waves wavefronts per ant).
     rows: (count, n) float32 torch tensor on the GPU; feasible: (count, n)
     uint8; u: (count,) float32.  Returns a (count,) int32 tensor."""
     import torch
@@ -307,10 +311,11 @@ def test_select(rows, feasible, u, tile: int = 8, stream=None):
     feas = feasible.to(torch.uint8).contiguous()
     uu = u.to(torch.float32).contiguous()
     out = torch.empty(count, dtype=torch.int32, device=rows.device)
-    _check(lib.aco_test_select(tile, n, count, ctypes.c_void_p(padded.data_ptr()),
-                               ctypes.c_void_p(feas.data_ptr()), ctypes.c_void_p(uu.data_ptr()),
-                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
-           "aco_test_select")
+    _check(lib.aco_test_select_shape(tile, waves, n, count, ctypes.c_void_p(padded.data_ptr()),
+                                     ctypes.c_void_p(feas.data_ptr()),
+                                     ctypes.c_void_p(uu.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+           "aco_test_select_shape")
     return out
 
 
@@ -339,6 +344,19 @@ def set_tile(n_lo: int, n_hi: int, cities_per_lane: int):
     _check(lib.aco_set_tile(n_lo, n_hi, cities_per_lane), "aco_set_tile")
 
 
+def set_shape(n_lo: int, n_hi: int, cities_per_lane: int, waves_per_ant: int):
+    """Construction shape for sizes n_lo..n_hi (aco_set_shape)."""
+    _check(lib.aco_set_shape(n_lo, n_hi, cities_per_lane, waves_per_ant), "aco_set_shape")
+
+
+def get_waves(n: int) -> int:
+    return int(lib.aco_get_waves(n))
+
+
+# (cities per lane, wavefronts per ant) of the autotuner's ms columns
+SHAPES = ((4, 1), (8, 1), (8, 2), (4, 2), (4, 4))
+
+
 def reset_tiles():
     """Restores the library's default construction tiles (aco_reset_tiles)."""
     lib.aco_reset_tiles()
@@ -349,23 +367,25 @@ def get_tile(n: int) -> int:
 
 
 def autotune(sizes, reps: int = 3, device="cuda", stream=None):
-    """Times every construction tile on synthetic instances of the given
-    sizes (m = n) and sets the tile table; returns (chosen, ms4, ms8)."""
+    """Times every construction shape on synthetic instances of the given
+    sizes (m = n) and sets the shape table; returns (chosen_tile,
+    chosen_waves, ms) with ms of shape (len(sizes), len(SHAPES)), -1 where a
+    shape does not support the size."""
     import torch
 
     sizes = np.ascontiguousarray(sorted(int(x) for x in sizes), np.int32)
     k = len(sizes)
     nbytes = workspace_bytes(int(sizes[-1]), int(sizes[-1]), atomic=False)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    chosen = np.zeros(k, np.int32)
-    ms4 = np.zeros(k, np.float32)
-    ms8 = np.zeros(k, np.float32)
+    tiles = np.zeros(k, np.int32)
+    waves = np.zeros(k, np.int32)
+    ms = np.zeros((k, len(SHAPES)), np.float32)
     _check(lib.aco_autotune(ctypes.c_void_p(ws.data_ptr()), nbytes,
                             sizes.ctypes.data_as(ctypes.c_void_p), k, reps,
-                            _stream_handle(stream), chosen.ctypes.data_as(ctypes.c_void_p),
-                            ms4.ctypes.data_as(ctypes.c_void_p),
-                            ms8.ctypes.data_as(ctypes.c_void_p)), "aco_autotune")
-    return chosen, ms4, ms8
+                            _stream_handle(stream), tiles.ctypes.data_as(ctypes.c_void_p),
+                            waves.ctypes.data_as(ctypes.c_void_p),
+                            ms.ctypes.data_as(ctypes.c_void_p)), "aco_autotune")
+    return tiles, waves, ms
 
 
 class Batch:

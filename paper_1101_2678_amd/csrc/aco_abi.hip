@@ -130,7 +130,8 @@ bool dist_valid(const int32_t* d, int n, int m, std::string* why) {
     return true;
 }
 
-Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile) {
+Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile,
+             int waves) {
     Colony col{};
     col.n = p.n;
     col.m = p.m;
@@ -156,6 +157,7 @@ Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, 
     col.iter_dev = reinterpret_cast<uint32_t*>(base + L.iter);
     col.delta = with_delta ? reinterpret_cast<double*>(base + L.delta) : nullptr;
     col.tile = tile;
+    col.waves = waves;
     return col;
 }
 
@@ -170,21 +172,27 @@ hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t b
     return e;
 }
 
-// Construction tile per instance size.  Default: 4 cities per lane up to
-// n = 256, 8 above (single-instance construction with m = n on MI355X: tile 4
-// about 3% faster at n = 64..256, tile 8 about 10% faster at 512..1024).  The
-// table is filled once, on first use, by a function-local static (thread-safe
-// initialisation); changing it while other threads read it is not supported.
+// Construction shape per instance size: the tile (cities per lane) and the
+// wavefronts per ant.  Default: 4 cities per lane up to n = 256, 8 above,
+// one wavefront per ant (single-instance construction with m = n on MI355X:
+// tile 4 about 3% faster at n = 64..256, tile 8 about 10% faster at
+// 512..1024).  The table is filled once, on first use, by a function-local
+// static (thread-safe initialisation); changing it while other threads read
+// it is not supported.
 namespace {
 constexpr int kTile4Max = 256;
 
-void fill_default_tiles(int8_t* t) {
-    for (int n = 0; n <= kMaxCities; ++n) t[n] = n <= kTile4Max ? 4 : 8;
+struct Shape {
+    int8_t tile, waves;
+};
+
+void fill_default_tiles(Shape* t) {
+    for (int n = 0; n <= kMaxCities; ++n) t[n] = Shape{(int8_t)(n <= kTile4Max ? 4 : 8), 1};
 }
 
-int8_t* tile_table() {
-    static int8_t* const table = [] {
-        static int8_t t[kMaxCities + 1];
+Shape* tile_table() {
+    static Shape* const table = [] {
+        static Shape t[kMaxCities + 1];
         fill_default_tiles(t);
         return t;
     }();
@@ -207,17 +215,27 @@ hipError_t device_shape(int* cus, size_t* lds_per_cu) {
 }
 
 int tile_for(int n) {
-    return (n >= 0 && n <= kMaxCities) ? tile_table()[n] : 8;
+    return (n >= 0 && n <= kMaxCities) ? tile_table()[n].tile : 8;
 }
 
-bool set_tile_range(int lo, int hi, int tile) {
+int waves_for(int n) {
+    return (n >= 0 && n <= kMaxCities) ? tile_table()[n].waves : 1;
+}
+
+bool shape_supported(int tile, int waves, int n) {
+    return waves == 1 ? tile_supported(tile, n) : split_supported(tile, waves, n);
+}
+
+bool set_shape_range(int lo, int hi, int tile, int waves) {
     if (lo < 1 || hi > kMaxCities || lo > hi) return false;
     for (int n = lo; n <= hi; ++n)
-        if (!tile_supported(tile, n)) return false;
-    int8_t* t = tile_table();
-    for (int n = lo; n <= hi; ++n) t[n] = (int8_t)tile;
+        if (!shape_supported(tile, waves, n)) return false;
+    Shape* t = tile_table();
+    for (int n = lo; n <= hi; ++n) t[n] = Shape{(int8_t)tile, (int8_t)waves};
     return true;
 }
+
+bool set_tile_range(int lo, int hi, int tile) { return set_shape_range(lo, hi, tile, 1); }
 
 }  // namespace host
 }  // namespace aco
@@ -321,7 +339,7 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     c->scratch_err = aco::host::noalloc_scratch(device, &c->scratch);
     c->has_atomic = ws_bytes >= L.atomic_end;
     c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic,
-                              aco::host::tile_for(p->n));
+                              aco::host::tile_for(p->n), aco::host::waves_for(p->n));
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ws_bytes = ws_bytes;
     hipError_t e = aco::host::upload_and_init(c->col, dist_host, L.base_end, c->stream);
@@ -342,7 +360,20 @@ aco_status aco_set_tile(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane) {
     return ACO_OK;
 }
 
+aco_status aco_set_shape(int32_t n_lo, int32_t n_hi, int32_t cities_per_lane,
+                         int32_t waves_per_ant) {
+    if (!aco::host::set_shape_range(n_lo, n_hi, cities_per_lane, waves_per_ant))
+        return fail(ACO_ERR_INVALID,
+                    "shape not supported over the range: 1 wavefront per ant with tile 8 (any "
+                    "n) or 4 (n <= 1024); 2 or 4 wavefronts only for n <= 1024 with at least "
+                    "as many passes of 64 * tile cities (tile 8: 2 waves; tile 4: 2 waves, or "
+                    "4 waves at 4 passes)");
+    return ACO_OK;
+}
+
 int32_t aco_get_tile(int32_t n) { return aco::host::tile_for(n); }
+
+int32_t aco_get_waves(int32_t n) { return aco::host::waves_for(n); }
 
 void aco_reset_tiles(void) { aco::host::reset_tiles(); }
 
@@ -566,29 +597,42 @@ aco_status aco_describe(aco_ctx* c, char* buf, size_t len) {
     (void)hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
     const int pass = 64 * col.tile;
     std::snprintf(buf, len,
-                  "construct=wave_per_ant cities_per_lane=%d passes=%d blocks=%d ld=%d "
-                  "ants_per_cu=%d cus=%d lds_per_cu=%d update_gather_threads=256 "
-                  "atomic=%d nn=%d",
-                  col.tile, (col.n + pass - 1) / pass, (col.n + 63) / 64, col.ld,
+                  "construct=workgroup_per_ant waves_per_ant=%d cities_per_lane=%d passes=%d "
+                  "blocks=%d ld=%d ants_per_cu=%d cus=%d lds_per_cu=%d "
+                  "update_gather_threads=256 atomic=%d nn=%d",
+                  col.waves, col.tile, (col.n + pass - 1) / pass, (col.n + 63) / 64, col.ld,
                   aco::construct_occupancy(col), cus, lds_cu, c->has_atomic ? 1 : 0, c->nn.nn);
+    return ACO_OK;
+}
+
+aco_status aco_test_select_shape(int32_t tile, int32_t waves, int32_t n, int32_t count,
+                                 const float* rows_dev, const uint8_t* feasible_dev,
+                                 const float* u_dev, int32_t* out_dev, void* hip_stream) {
+    if (n < 1 || n > aco::kMaxCities) return fail(ACO_ERR_INVALID, "n must be in [1, 4096]");
+    if (!aco::host::shape_supported(tile, waves, n))
+        return fail(ACO_ERR_INVALID, "construction shape not supported for this n");
+    if (count < 0) return fail(ACO_ERR_INVALID, "count must be >= 0");
+    if (count > 0 && (!rows_dev || !feasible_dev || !u_dev || !out_dev))
+        return fail(ACO_ERR_INVALID, "NULL device pointer");
+    if (((uintptr_t)rows_dev % 16) != 0)
+        return fail(ACO_ERR_INVALID, "rows must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e =
+        waves == 1 ? aco::launch_test_select(tile, n, count, rows_dev, feasible_dev, u_dev,
+                                             out_dev, s)
+                   : aco::launch_test_select_split(tile, waves, n, count, rows_dev,
+                                                   feasible_dev, u_dev, out_dev, s);
+    if (e != hipSuccess) return device_fail(nullptr, e, "aco_test_select");
     return ACO_OK;
 }
 
 aco_status aco_test_select(int32_t tile, int32_t n, int32_t count, const float* rows_dev,
                            const uint8_t* feasible_dev, const float* u_dev, int32_t* out_dev,
                            void* hip_stream) {
-    if (n < 1 || n > aco::kMaxCities) return fail(ACO_ERR_INVALID, "n must be in [1, 4096]");
-    if (!aco::tile_supported(tile, n))
+    if (n >= 1 && n <= aco::kMaxCities && !aco::tile_supported(tile, n))
         return fail(ACO_ERR_INVALID, "tile must be 8 (any n) or 4 (n <= 1024)");
-    if (count < 0) return fail(ACO_ERR_INVALID, "count must be >= 0");
-    if (count > 0 && (!rows_dev || !feasible_dev || !u_dev || !out_dev))
-        return fail(ACO_ERR_INVALID, "NULL device pointer");
-    if (((uintptr_t)rows_dev % 16) != 0)
-        return fail(ACO_ERR_INVALID, "rows must be 16-byte aligned");
-    const hipError_t e = aco::launch_test_select(tile, n, count, rows_dev, feasible_dev, u_dev,
-                                                 out_dev, static_cast<hipStream_t>(hip_stream));
-    if (e != hipSuccess) return device_fail(nullptr, e, "aco_test_select");
-    return ACO_OK;
+    return aco_test_select_shape(tile, 1, n, count, rows_dev, feasible_dev, u_dev, out_dev,
+                                 hip_stream);
 }
 
 aco_status aco_probe_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {

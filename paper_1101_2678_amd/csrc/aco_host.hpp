@@ -33,14 +33,19 @@ aco_status stream_on_device(void* hip_stream, int device, const char* where);
 bool params_valid(const aco_params* p, std::string* why);
 bool dist_valid(const int32_t* d, int n, int m, std::string* why);
 Layout make_layout(const aco_params& p);
-Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile);
+Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile,
+             int waves = 1);
 // Clears the colony's base arrays, uploads the distances and enqueues the
 // initialisation kernels (nearest-neighbour tour, tau0, tau and choice fill).
 hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t base_bytes,
                            hipStream_t stream);
 // Compute units and LDS bytes per compute unit of the current device.
 hipError_t device_shape(int* cus, size_t* lds_per_cu);
+// Construction shape table: tile (cities per lane) and wavefronts per ant by n.
 int tile_for(int n);
+int waves_for(int n);
+bool shape_supported(int tile, int waves, int n);
+bool set_shape_range(int lo, int hi, int tile, int waves);
 bool set_tile_range(int lo, int hi, int tile);
 void reset_tiles();
 

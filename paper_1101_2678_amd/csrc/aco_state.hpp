@@ -32,6 +32,7 @@ struct Colony {
     double* delta;       // n x ld binary64 deposits (atomic update), or null
     uint32_t* iter_dev;  // next iteration (batched path; advanced on the device)
     int32_t tile;        // construction tile: cities per lane per pass (4 or 8)
+    int32_t waves;       // construction wavefronts per ant (1, or 2 / 4 for n <= 1024)
 };
 
 constexpr int kMaxCities = 4096;
@@ -44,6 +45,15 @@ constexpr int kMaxNoallocCities = 1024;
 // for n cities.
 bool tile_supported(int tile, int n);
 hipError_t launch_construct(const Colony& c, uint32_t iter, hipStream_t s);
+// Several wavefronts per ant (c.waves > 1): rows of at most kMaxSplitCities
+// cities, W = 2 or 4 waves sharing the passes of tile c.tile, W <= passes.
+constexpr int kMaxSplitCities = 1024;
+bool split_supported(int tile, int waves, int n);
+hipError_t launch_construct_split(const Colony& c, uint32_t iter, hipStream_t s);
+int construct_split_occupancy(const Colony& c);
+hipError_t launch_test_select_split(int tile, int waves, int n, int count, const float* rows,
+                                    const uint8_t* feasible, const float* u, int32_t* out,
+                                    hipStream_t s);
 // One workgroup per entry of antmap: (colony << 16) | ant.  max_n, the largest
 // n among the colonies, picks the kernel's pass bound, so it must not be
 // smaller than any colony's n; lds (dynamic LDS per workgroup, from

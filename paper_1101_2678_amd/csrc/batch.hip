@@ -427,8 +427,10 @@ aco_status aco_batch_autotune(aco_batch* b, const aco_batch_config* cands, int32
 }
 
 aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes, int32_t count,
-                        int32_t reps, void* hip_stream, int32_t* chosen, float* ms_tile4,
-                        float* ms_tile8) {
+                        int32_t reps, void* hip_stream, int32_t* chosen_tile,
+                        int32_t* chosen_waves, float* ms) {
+    // The shapes timed, in the order of ms's columns (aco.h).
+    constexpr int kShapes[ACO_NUM_SHAPES][2] = {{4, 1}, {8, 1}, {8, 2}, {4, 2}, {4, 4}};
     aco::host::g_error.clear();
     if (!sizes || count < 1) return fail(ACO_ERR_INVALID, "need at least one size");
     if (reps < 1) return fail(ACO_ERR_INVALID, "reps must be >= 1");
@@ -448,19 +450,19 @@ aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    std::vector<int> best(count, 8);
+    std::vector<int> best(count, 1);  // index into kShapes
     for (int i = 0; i < count && e == hipSuccess; ++i) {
         const int n = sizes[i];
         const aco_params p{n, n, 1, 2, 0.5f, 1};
         const aco::host::Layout L = aco::host::make_layout(p);
         const std::vector<int32_t> d = tuning_instance(n);
         float t_best = 1e30f;
-        for (int tile : {4, 8}) {
-            float* out = tile == 4 ? ms_tile4 : ms_tile8;
-            if (out) out[i] = -1.0f;
-            if (!aco::tile_supported(tile, n)) continue;
+        for (int k = 0; k < ACO_NUM_SHAPES; ++k) {
+            const int tile = kShapes[k][0], waves = kShapes[k][1];
+            if (ms) ms[(size_t)i * ACO_NUM_SHAPES + k] = -1.0f;
+            if (!aco::host::shape_supported(tile, waves, n)) continue;
             const aco::Colony col =
-                aco::host::carve(static_cast<char*>(d_workspace), L, p, false, tile);
+                aco::host::carve(static_cast<char*>(d_workspace), L, p, false, tile, waves);
             e = aco::host::upload_and_init(col, d.data(), L.base_end, s);
             if (e == hipSuccess) e = aco::launch_construct(col, 0, s);  // warm-up
             if (e == hipSuccess) e = hipEventRecord(e0, s);
@@ -468,32 +470,37 @@ aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes
                 e = aco::launch_construct(col, (uint32_t)r + 1u, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
             if (e != hipSuccess) break;
-            ms /= (float)reps;
-            if (out) out[i] = ms;
-            if (ms < t_best) {
-                t_best = ms;
-                best[i] = tile;
+            t /= (float)reps;
+            if (ms) ms[(size_t)i * ACO_NUM_SHAPES + k] = t;
+            if (t < t_best) {
+                t_best = t;
+                best[i] = k;
             }
         }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (e != hipSuccess) return aco::host::device_fail(nullptr, e, "aco_autotune");
-    // Size bucket i covers (sizes[i-1], sizes[i]]; the last bucket runs to 4096.
+    // Size bucket i covers (sizes[i-1], sizes[i]]; the last bucket runs to
+    // 4096.  A size of the bucket that the chosen shape does not support takes
+    // the chosen tile with one wavefront, or tile 8 where tile 4 stops.
     for (int i = 0; i < count; ++i) {
         const int lo = i == 0 ? 1 : sizes[i - 1] + 1;
         const int hi = i == count - 1 ? aco::kMaxCities : sizes[i];
-        if (best[i] == 4) {
-            const int top = std::min(hi, aco::kMaxTile4Cities);
-            if (lo <= top) aco::host::set_tile_range(lo, top, 4);
-            if (top < hi) aco::host::set_tile_range(std::max(lo, top + 1), hi, 8);
-        } else {
-            aco::host::set_tile_range(lo, hi, 8);
+        const int tile = kShapes[best[i]][0], waves = kShapes[best[i]][1];
+        for (int n = lo; n <= hi; ++n) {
+            if (aco::host::shape_supported(tile, waves, n))
+                aco::host::set_shape_range(n, n, tile, waves);
+            else if (aco::tile_supported(tile, n))
+                aco::host::set_shape_range(n, n, tile, 1);
+            else
+                aco::host::set_shape_range(n, n, 8, 1);
         }
-        if (chosen) chosen[i] = best[i];
+        if (chosen_tile) chosen_tile[i] = tile;
+        if (chosen_waves) chosen_waves[i] = waves;
     }
     return ACO_OK;
 }

@@ -1,0 +1,97 @@
+// r64_lanes.hpp -- pieces of the R64 roulette step shared by the
+// construction kernels with one and with several wavefronts per ant: the
+// tile of cities per lane, the masking of visited cities, the in-lane and
+// cross-lane pairwise block sums, the per-block visited bits, the buffer view
+// of a choice row and the per-step uniform draws (Section II, Eq. 1).
+#pragma once
+
+#include "aco_device.hpp"
+#include "aco_state.hpp"
+
+namespace aco {
+namespace {
+
+constexpr float kBlockSlack = 1.00000095367431640625f;  // 1 + 2^-20
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Cities per lane per pass (G), and what follows from it.
+template <int G>
+struct Tile {
+    static_assert(G == 4 || G == 8, "tile must be 4 or 8 cities per lane");
+    static constexpr int kPass = 64 * G;          // cities per pass
+    static constexpr int kLanesPerBlock = 64 / G; // lanes holding one 64-city block
+    static constexpr int kMaxPasses = 64 / G;     // lane bit set holds 64 bits
+};
+
+// Visited bits of block b, kept in lane b of a register pair: bit t set <=>
+// city 64b + t is visited or does not exist.
+__device__ __forceinline__ uint64_t initial_block_bits(int n, int b) {
+    const int valid = n - 64 * b;
+    if (valid <= 0) return ~0ull;
+    if (valid >= 64) return 0ull;
+    return ~0ull << valid;
+}
+
+// The value lane l holds in v, on every lane (l wave-uniform).
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Buffer view of one choice row: loads at or beyond `valid_bytes` return 0
+// without touching memory.  valid_bytes is n rounded up to 4 cities, so a
+// 16-byte load is either wholly inside or wholly outside the row; the padding
+// columns between n and that bound hold zeros.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int valid_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, valid_bytes,
+                                             0x00020000);
+}
+
+// Sign-extended bit `e` of `bits` (0 or all ones).  Written as v_bfe_i32 so
+// the masking of one city costs two VALU operations (extract, and).
+template <int E>
+__device__ __forceinline__ uint32_t bit_mask(uint32_t bits) {
+    uint32_t m;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(bits), "i"(E));
+    return m;
+}
+
+template <int E0>
+__device__ __forceinline__ void mask4(u32x4& v, uint32_t bits) {
+    v.x &= bit_mask<E0 + 0>(bits);
+    v.y &= bit_mask<E0 + 1>(bits);
+    v.z &= bit_mask<E0 + 2>(bits);
+    v.w &= bit_mask<E0 + 3>(bits);
+}
+
+__device__ __forceinline__ float pair_sum4(const u32x4& v) {
+    return (__uint_as_float(v.x) + __uint_as_float(v.y)) +
+           (__uint_as_float(v.z) + __uint_as_float(v.w));
+}
+
+// Balanced pairwise sum over groups of LANES consecutive lanes (LANES = 8 or
+// 16, inside one 16-lane DPP row); the last lane of each group ends with it.
+template <int LANES>
+__device__ __forceinline__ float group_pairwise(float x) {
+    x = x + dpp_move<0x111, 0xF>(x);
+    x = x + dpp_move<0x112, 0xF>(x);
+    x = x + dpp_move<0x114, 0xF>(x);
+    if (LANES == 16) x = x + dpp_move<0x118, 0xF>(x);
+    return x;
+}
+
+// Uniform draws for steps s0 .. s0+63: lane t holds u of step s0 + t.  The
+// counter words differ per lane, so the ten Philox rounds run on the vector
+// unit once per 64 steps instead of on the scalar unit every step.
+__device__ __forceinline__ float draws64(PhiloxKey key, uint32_t iter, uint32_t ant, int s0,
+                                         int lane) {
+    return uniform24(draw(key, iter, ant, (uint32_t)(s0 + lane)));
+}
+
+__host__ __device__ size_t tour_lds_bytes(int n) {
+    return ((size_t)(n + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
+}
+
+}  // namespace
+}  // namespace aco

@@ -146,6 +146,37 @@ def test_tile_table(aco):
     assert [aco.get_tile(n) for n in (150, 300)] == [4, 8]
 
 
+def test_shape_table(aco):
+    """Several wavefronts per ant: n <= 1024, at least as many passes of
+    64 * tile cities as waves; tile 8 with 2 waves, tile 4 with 2, or with 4
+    at four passes.  Rejected ranges leave the table unchanged."""
+    aco.reset_tiles()
+    assert [aco.get_waves(n) for n in (3, 1000, 4096)] == [1, 1, 1]
+    aco.set_shape(513, 1024, 8, 2)
+    aco.set_shape(257, 512, 4, 2)
+    aco.set_shape(769, 1024, 4, 4)
+    assert [(aco.get_tile(n), aco.get_waves(n)) for n in (256, 257, 512, 513, 768, 769, 1024,
+                                                         1025)] == [
+        (4, 1), (4, 2), (4, 2), (8, 2), (8, 2), (4, 4), (4, 4), (8, 1)]
+    for bad in ((512, 600, 8, 2),    # n = 512 is one pass of tile 8
+                (200, 300, 4, 2),    # n <= 256 is one pass of tile 4
+                (700, 800, 4, 4),    # three passes below 769
+                (1000, 1100, 8, 2),  # beyond 1024 cities
+                (600, 700, 8, 4), (600, 700, 4, 3), (600, 700, 4, 8)):
+        with pytest.raises(aco.AcoError):
+            aco.set_shape(*bad)
+    assert aco.get_waves(1000) == 4 and aco.get_waves(600) == 2
+    aco.set_tile(1, 1024, 8)  # the tile setter means one wavefront
+    assert aco.get_waves(1000) == 1
+    aco.reset_tiles()
+    assert [(aco.get_tile(n), aco.get_waves(n)) for n in (100, 1000)] == [(4, 1), (8, 1)]
+    sel = aco.lib.aco_test_select_shape
+    assert sel(8, 2, 512, 0, None, None, None, None, None) == aco.ACO_ERR_INVALID
+    assert sel(4, 4, 700, 0, None, None, None, None, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 2, 1000, 1, None, None, None, None, None) == aco.ACO_ERR_INVALID
+    assert sel(8, 2, 1000, 0, None, None, None, None, None) == aco.ACO_OK
+
+
 def test_batch_workspace_and_validation(aco):
     P = aco.Params
     arr = (P * 3)(P(100, 100, 1, 2, 0.5, 1), P(50, 20, 1, 2, 0.5, 2), P(700, 700, 1, 2, 0.5, 3))

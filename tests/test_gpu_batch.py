@@ -231,16 +231,29 @@ def test_graph_replays_with_eager_work_between():
 
 
 def test_autotune_sets_table_and_keeps_results():
+    """The autotuner times every shape that supports each size, fills the
+    shape table with the fastest, and the chosen shapes give the oracle's
+    results."""
     from paper_1101_2678_amd import aco
 
     try:
-        chosen, ms4, ms8 = aco.autotune([128, 512, 1024, 2400], reps=2)
-        log(f"  autotune chosen={chosen.tolist()} ms4={ms4.tolist()} ms8={ms8.tolist()}")
-        assert set(chosen.tolist()) <= {4, 8}
-        assert ms4[-1] == -1.0 and (ms8 > 0).all()
-        assert aco.get_tile(2400) == 8 and aco.get_tile(4096) == 8
-        _, d = tsp_inputs.instance(300, "uniform", side=1_000_000, seed=9)
-        compare_run(d, 80, 1, 2, 0.5, 9, 2, kinds=("gather",))
+        tiles, waves, ms = aco.autotune([128, 512, 1000, 2400], reps=2)
+        log(f"  autotune tiles={tiles.tolist()} waves={waves.tolist()} ms={ms.tolist()}")
+        assert set(tiles.tolist()) <= {4, 8} and set(waves.tolist()) <= {1, 2, 4}
+        supported = ms > 0
+        # (4, 1) (8, 1) (8, 2) (4, 2) (4, 4) per size
+        assert supported.tolist() == [[True, True, False, False, False],
+                                      [True, True, False, True, False],
+                                      [True, True, True, True, True],
+                                      [False, True, False, False, False]]
+        for i, n in enumerate((128, 512, 1000, 2400)):
+            k = aco.SHAPES.index((int(tiles[i]), int(waves[i])))
+            assert ms[i, k] == ms[i][supported[i]].min()
+            assert aco.get_tile(n) == tiles[i] and aco.get_waves(n) == waves[i]
+        assert aco.get_tile(4096) == 8 and aco.get_waves(4096) == 1
+        for n in (300, 1000):
+            _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=9)
+            compare_run(d, 80, 1, 2, 0.5, 9, 2, kinds=("gather",))
     finally:
         aco.reset_tiles()
 
