@@ -57,7 +57,8 @@ __device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& lane_bit
     if (lane == (j >> 6)) block_bits |= 1ull << (j & 63);
     const int owner = (j % Tile<G>::kPass) / G;
     const int bit = (j / Tile<G>::kPass) * G + (j % G);
-    if (lane == owner) lane_bits &= ~(1ull << bit);
+    // a select rather than a branch around the owner lane
+    lane_bits &= lane == owner ? ~(1ull << bit) : ~0ull;
 }
 
 // Stages the masked weights of block `b` into s_w (city 64b + t at
@@ -158,27 +159,30 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
     const float E = wave_shift_up1(I);
     const float bound = E + T * kBlockSlack;
     uint64_t cand = ballot(bound > target) & (nb >= 64 ? ~0ull : (1ull << nb) - 1ull);
-    while (cand) {
-        const int b = __builtin_ctzll(cand);
-        cand &= cand - 1;
-        float w;
-        if (kAll) {
-            w = s_w[b * 64 + lane];
-        } else {
-            stage_block<G, P>(wa, wb, b, s_w, lane);
-            w = s_w[(b % G) * 64 + lane];
-        }
-        const uint64_t vis = lane_u64(block_bits, b);
-        const float s = s64_scan(w);
-        const float eb = read_lane(E, b);
-        const uint64_t hit = ballot((eb + s) > target) & ~vis;
-        if (hit) return b * 64 + __builtin_ctzll(hit);
+    // Nearly always exactly one candidate block: a single-exit loop, tested
+    // at the bottom, so that the usual step runs through without a taken
+    // branch.
+    int j = -1;
+    if (__builtin_expect(cand != 0, 1)) {
+        do {
+            const int b = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            float w;
+            if (kAll) {
+                w = s_w[b * 64 + lane];
+            } else {
+                stage_block<G, P>(wa, wb, b, s_w, lane);
+                w = s_w[(b % G) * 64 + lane];
+            }
+            const uint64_t vis = lane_u64(block_bits, b);
+            const float s = s64_scan(w);
+            const float eb = read_lane(E, b);
+            const uint64_t hit = ballot((eb + s) > target) & ~vis;
+            if (hit) j = b * 64 + __builtin_ctzll(hit);
+        } while (__builtin_expect(j < 0 && cand != 0, 0));
     }
-    // No prefix exceeds the target: the highest feasible city.
-    const uint64_t live = ballot(~block_bits != 0ull);
-    if (!live) return -1;
-    const int b = 63 - __builtin_clzll(live);
-    return b * 64 + 63 - __builtin_clzll(~lane_u64(block_bits, b));
+    if (__builtin_expect(j >= 0, 1)) return j;
+    return pick_fallback(block_bits);
 }
 
 template <int G, int P, bool GUARD, bool SKIP>
@@ -219,7 +223,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
         const int slot = (step - 1) & 63;
-        if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
+        if (__builtin_expect(slot == 0, 0)) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const float* row = c.choice + (size_t)cur * c.ld;
         int j = r64_pick<G, P, GUARD, SKIP>(row, n, np, lane_bits, block_bits, sh.T, sh.w, u,

@@ -45,10 +45,9 @@ __device__ __forceinline__ void mark_visited_split(int j, int wv, int lane, uint
                                                    uint64_t& block_bits) {
     if (lane == (j >> 6)) block_bits |= 1ull << (j & 63);
     const int p = j / Tile<G>::kPass;
-    if (p % W != wv) return;
     const int owner = (j % Tile<G>::kPass) / G;
     const int bit = (p / W) * G + (j % G);
-    if (lane == owner) lane_bits &= ~(1ull << bit);
+    lane_bits &= (p % W == wv && lane == owner) ? ~(1ull << bit) : ~0ull;
 }
 
 // One R64 draw over row `row` by the W waves of the workgroup; s_T and s_w
@@ -98,20 +97,22 @@ __device__ __forceinline__ int pick_split(const float* __restrict__ row, int n, 
     const float E = wave_shift_up1(I);
     const float bound = E + T * kBlockSlack;
     uint64_t cand = ballot(bound > target) & ((1ull << nb) - 1ull);
-    while (cand) {
-        const int b = __builtin_ctzll(cand);
-        cand &= cand - 1;
-        const float w = s_w[b * 64 + lane];
-        const uint64_t vis = lane_u64(block_bits, b);
-        const float s = s64_scan(w);
-        const float eb = read_lane(E, b);
-        const uint64_t hit = ballot((eb + s) > target) & ~vis;
-        if (hit) return b * 64 + __builtin_ctzll(hit);
+    // as in the single-wave kernel: one bottom-tested loop, rarely repeated
+    int j = -1;
+    if (__builtin_expect(cand != 0, 1)) {
+        do {
+            const int b = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            const float w = s_w[b * 64 + lane];
+            const uint64_t vis = lane_u64(block_bits, b);
+            const float s = s64_scan(w);
+            const float eb = read_lane(E, b);
+            const uint64_t hit = ballot((eb + s) > target) & ~vis;
+            if (hit) j = b * 64 + __builtin_ctzll(hit);
+        } while (__builtin_expect(j < 0 && cand != 0, 0));
     }
-    const uint64_t live = ballot(~block_bits != 0ull);
-    if (!live) return -1;
-    const int b = 63 - __builtin_clzll(live);
-    return b * 64 + 63 - __builtin_clzll(~lane_u64(block_bits, b));
+    if (__builtin_expect(j >= 0, 1)) return j;
+    return pick_fallback(block_bits);
 }
 
 template <int G, int W, int PW>
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(64 * W) void k_construct_split(Colony c, uint32_t i
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
         const int slot = (step - 1) & 63;
-        if (slot == 0) u64 = draws64(key, iter, (uint32_t)k, step, lane);
+        if (__builtin_expect(slot == 0, 0)) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const int buf = step & 1;
         int j = pick_split<G, W, PW>(c.choice + (size_t)cur * c.ld, n, np, wv, lane_bits,

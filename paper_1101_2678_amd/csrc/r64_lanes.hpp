@@ -39,6 +39,15 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// No prefix exceeds the target (rounding, or every weight zero): the highest
+// feasible city, or -1 if there is none.
+__device__ __forceinline__ int pick_fallback(uint64_t block_bits) {
+    const uint64_t live = ballot(~block_bits != 0ull);
+    if (!live) return -1;
+    const int b = 63 - __builtin_clzll(live);
+    return b * 64 + 63 - __builtin_clzll(~lane_u64(block_bits, b));
+}
+
 // Buffer view of one choice row: loads at or beyond `valid_bytes` return 0
 // without touching memory.  valid_bytes is n rounded up to 4 cities, so a
 // 16-byte load is either wholly inside or wholly outside the row; the padding
