@@ -202,7 +202,7 @@ struct AntShared {
 
 // The whole tour of ant k of colony c in iteration `iter`: placement, n - 1
 // roulette steps, then length, deposit, tour and neighbour tables.
-template <int G, int P, bool GUARD, bool SKIP>
+template <int G, int P, bool GUARD, bool SKIP, bool LOAD_FIRST>
 __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t iter,
                                               uint16_t* s_tour, AntShared& sh) {
     const int lane = threadIdx.x;
@@ -217,24 +217,48 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
 
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
-    if (lane == 0) s_tour[0] = (uint16_t)cur;
-    mark_visited<G>(cur, lane, lane_bits, block_bits);
 
+    // LOAD_FIRST: a step's row loads go out as soon as its city is known, and
+    // the bookkeeping of that city (tour entry, visited bits) is done while
+    // they are in flight.  That shortens latency-bound launches (one or two
+    // passes: n = 1000 7%, n = 100 14% faster) but made the bandwidth-bound
+    // n = 2400 launch 1% slower, which keeps the bookkeeping first.  With
+    // LOAD_FIRST the loads see the visited bits without the step's own city;
+    // with SKIP that only loads a quad once more, and masking (which sees
+    // it) zeroes the city.
     float u64 = 0.0f;
-    for (int step = 1; step < n; ++step) {
-        const int slot = (step - 1) & 63;
-        if (__builtin_expect(slot == 0, 0)) u64 = draws64(key, iter, (uint32_t)k, step, lane);
-        const float u = read_lane(u64, slot);
-        const float* row = c.choice + (size_t)cur * c.ld;
-        int j = r64_pick<G, P, GUARD, SKIP>(row, n, np, lane_bits, block_bits, sh.T, sh.w, u,
-                                            lane);
-        // At every step n - step >= 1 cities are unvisited, so j >= 0; the
-        // clamp only keeps the LDS indices in range should that ever break.
-        j = j < 0 ? 0 : j;
-        if (lane == 0) s_tour[step] = (uint16_t)j;
-        mark_visited<G>(j, lane, lane_bits, block_bits);
-        cur = j;
+    if (LOAD_FIRST) {
+        for (int step = 1; step < n; ++step) {
+            u32x4 wa[P], wb[P];
+            load_row<G, P, GUARD, SKIP>(c.choice + (size_t)cur * c.ld, n, np, lane_bits, lane,
+                                        wa, wb);
+            if (lane == 0) s_tour[step - 1] = (uint16_t)cur;
+            mark_visited<G>(cur, lane, lane_bits, block_bits);
+            const int slot = (step - 1) & 63;
+            if (__builtin_expect(slot == 0, 0))
+                u64 = draws64(key, iter, (uint32_t)k, step, lane);
+            const float u = read_lane(u64, slot);
+            const int j = pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, block_bits, sh.T,
+                                                   sh.w, u, lane);
+            // At every step n - step >= 1 cities are unvisited, so j >= 0;
+            // the clamp only keeps the LDS indices in range should that
+            // ever break.
+            cur = j < 0 ? 0 : j;
+        }
+    } else {
+        for (int step = 1; step < n; ++step) {
+            if (lane == 0) s_tour[step - 1] = (uint16_t)cur;
+            mark_visited<G>(cur, lane, lane_bits, block_bits);
+            const int slot = (step - 1) & 63;
+            if (__builtin_expect(slot == 0, 0))
+                u64 = draws64(key, iter, (uint32_t)k, step, lane);
+            const float u = read_lane(u64, slot);
+            const int j = r64_pick<G, P, GUARD, SKIP>(c.choice + (size_t)cur * c.ld, n, np,
+                                                      lane_bits, block_bits, sh.T, sh.w, u, lane);
+            cur = j < 0 ? 0 : j;
+        }
     }
+    if (lane == 0) s_tour[n - 1] = (uint16_t)cur;
     __syncthreads();
     if (lane == 0) s_tour[n] = s_tour[0];
     __syncthreads();
@@ -261,7 +285,8 @@ template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
     __shared__ __align__(16) AntShared sh;
-    construct_ant<G, P, false, (P >= 3)>(c, ant_of_block(blockIdx.x, c.m), iter, s_tour, sh);
+    construct_ant<G, P, false, (P >= 3), (P < 3)>(c, ant_of_block(blockIdx.x, c.m), iter,
+                                                  s_tour, sh);
 }
 
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
@@ -270,6 +295,10 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
 // P8 bounds the passes of tile-8 colonies (every colony of the launch has
 // n <= 512 P8), so a batch of small instances holds no registers for rows it
 // does not have; tile 4 is only ever set for n <= 1024 (4 passes).
+// Loads first in the batched launch too: 754 -> 761 solves/s on the
+// 256-instance workload (n 50..1000, same box).
+constexpr bool kBatchLoadFirst = true;
+
 template <int P8>
 __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict__ cols,
                                                         const uint32_t* __restrict__ antmap) {
@@ -283,9 +312,10 @@ __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict
     // becomes a loop over lanes.
     const uint32_t iter = __builtin_amdgcn_readfirstlane(*c.iter_dev);
     if (c.tile == 4)
-        construct_ant<4, 4, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+        construct_ant<4, 4, true, true, kBatchLoadFirst>(c, (int)(e & 0xffffu), iter, s_tour, sh);
     else
-        construct_ant<8, P8, true, true>(c, (int)(e & 0xffffu), iter, s_tour, sh);
+        construct_ant<8, P8, true, true, kBatchLoadFirst>(c, (int)(e & 0xffffu), iter, s_tour,
+                                                          sh);
 }
 
 template <int G, int P>

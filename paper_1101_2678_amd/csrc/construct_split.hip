@@ -50,16 +50,13 @@ __device__ __forceinline__ void mark_visited_split(int j, int wv, int lane, uint
     lane_bits &= (p % W == wv && lane == owner) ? ~(1ull << bit) : ~0ull;
 }
 
-// One R64 draw over row `row` by the W waves of the workgroup; s_T and s_w
-// are this step's buffers.  Returns the chosen city (the same in every
-// wave), or -1 if no city is feasible.
+// One R64 draw by the W waves of the workgroup over a row loaded with
+// load_split; s_T and s_w are this step's buffers.  Returns the chosen city
+// (the same in every wave), or -1 if no city is feasible.
 template <int G, int W, int PW>
-__device__ __forceinline__ int pick_split(const float* __restrict__ row, int n, int np, int wv,
-                                          uint64_t lane_bits, uint64_t block_bits, float* s_T,
-                                          float* s_w, float u, int lane) {
-    constexpr int LPB = Tile<G>::kLanesPerBlock;
+__device__ __forceinline__ void load_split(const float* __restrict__ row, int n, int np, int wv,
+                                           int lane, u32x4 (&wa)[PW], u32x4 (&wb)[PW]) {
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
-    u32x4 wa[PW], wb[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
         const int p = wv + W * q;
@@ -68,6 +65,14 @@ __device__ __forceinline__ int pick_split(const float* __restrict__ row, int n, 
         wa[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
         if (G == 8) wb[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
     }
+}
+
+// wa/wb as load_split leaves them (masked in place).
+template <int G, int W, int PW>
+__device__ __forceinline__ int pick_split(u32x4 (&wa)[PW], u32x4 (&wb)[PW], int n, int np,
+                                          int wv, uint64_t lane_bits, uint64_t block_bits,
+                                          float* s_T, float* s_w, float u, int lane) {
+    constexpr int LPB = Tile<G>::kLanesPerBlock;
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
         const int p = wv + W * q;
@@ -134,24 +139,26 @@ __global__ __launch_bounds__(64 * W) void k_construct_split(Colony c, uint32_t i
 
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
-    if (tid == 0) s_tour[0] = (uint16_t)cur;
-    mark_visited_split<G, W>(cur, wv, lane, lane_bits, block_bits);
 
+    // As in the single-wave kernel: a step's row loads go out first, the
+    // bookkeeping of its city follows them.
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
+        u32x4 wa[PW], wb[PW];
+        load_split<G, W, PW>(c.choice + (size_t)cur * c.ld, n, np, wv, lane, wa, wb);
+        if (tid == 0) s_tour[step - 1] = (uint16_t)cur;
+        mark_visited_split<G, W>(cur, wv, lane, lane_bits, block_bits);
         const int slot = (step - 1) & 63;
         if (__builtin_expect(slot == 0, 0)) u64 = draws64(key, iter, (uint32_t)k, step, lane);
         const float u = read_lane(u64, slot);
         const int buf = step & 1;
-        int j = pick_split<G, W, PW>(c.choice + (size_t)cur * c.ld, n, np, wv, lane_bits,
-                                     block_bits, sh.T[buf], sh.w[buf], u, lane);
+        const int j = pick_split<G, W, PW>(wa, wb, n, np, wv, lane_bits, block_bits, sh.T[buf],
+                                           sh.w[buf], u, lane);
         // n - step >= 1 cities are unvisited, so j >= 0; the clamp only keeps
         // the LDS indices in range should that ever break.
-        j = j < 0 ? 0 : j;
-        if (tid == 0) s_tour[step] = (uint16_t)j;
-        mark_visited_split<G, W>(j, wv, lane, lane_bits, block_bits);
-        cur = j;
+        cur = j < 0 ? 0 : j;
     }
+    if (tid == 0) s_tour[n - 1] = (uint16_t)cur;
     __syncthreads();
     if (tid == 0) s_tour[n] = s_tour[0];
     __syncthreads();
@@ -204,8 +211,10 @@ __global__ __launch_bounds__(64 * W) void k_test_select_split(const float* rows,
         }
     if (tid < 64) sh.T[0][lane] = 0.0f;
     __syncthreads();
-    const int j = pick_split<G, W, PW>(rows + (size_t)q * ld, n, np, wv, lane_bits, vis, sh.T[0],
-                                       sh.w[0], us[q], lane);
+    u32x4 wa[PW], wb[PW];
+    load_split<G, W, PW>(rows + (size_t)q * ld, n, np, wv, lane, wa, wb);
+    const int j = pick_split<G, W, PW>(wa, wb, n, np, wv, lane_bits, vis, sh.T[0], sh.w[0],
+                                       us[q], lane);
     if (tid == 0) out[q] = j;
 }
 
