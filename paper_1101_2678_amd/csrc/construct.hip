@@ -87,25 +87,31 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
     }
 }
 
-// Issues the loads of one choice row (ld-padded, zero beyond n) into wa/wb:
-// in pass p < np lane l takes cities 64Gp + Gl .. + G - 1.  With SKIP, a
-// 16-byte load whose four cities are all visited goes out of range instead
-// (it returns zeros and touches no memory).
+// Issues the loads of row `row` of the ld-padded matrix `mat` into wa/wb:
+// in pass p < np lane l takes cities 64Gp + Gl .. + G - 1.  The descriptor
+// spans `records` bytes from mat and stays the same for the whole tour; the
+// row is selected by the scalar offset (two scalar operations per step), and
+// the range check covers scalar plus vector offset.  Loads past the end of
+// the span return zeros without touching memory; those past the row's n
+// cities but inside the span read padding or the next row, and masking
+// (whose bits exist only for cities < n) zeroes them.  With SKIP, a 16-byte
+// load whose four cities are all visited goes out of range instead.
 template <int G, int P, bool GUARD, bool SKIP>
-__device__ __forceinline__ void load_row(const float* __restrict__ row, int n, int np,
-                                         uint64_t lane_bits, int lane, u32x4 (&wa)[P],
-                                         u32x4 (&wb)[P]) {
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
+__device__ __forceinline__ void load_row(const float* __restrict__ mat, int records, int row,
+                                         int ld, int np, uint64_t lane_bits, int lane,
+                                         u32x4 (&wa)[P], u32x4 (&wb)[P]) {
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(mat, records);
+    const int soff = row * ld * 4;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (GUARD && p >= np) break;
         const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
         const int off = (p * Tile<G>::kPass + lane * G) * 4;
         const int oa = (!SKIP || (bits & 0xFu)) ? off : kSkipOffset;
-        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, oa, 0, 0);
+        wa[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, oa, soff, 0);
         if (G == 8) {
             const int ob = (!SKIP || (bits & 0xF0u)) ? off + 16 : kSkipOffset;
-            wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, ob, 0, 0);
+            wb[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, ob, soff, 0);
         }
     }
 }
@@ -186,11 +192,12 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
 }
 
 template <int G, int P, bool GUARD, bool SKIP>
-__device__ __forceinline__ int r64_pick(const float* __restrict__ row, int n, int np,
-                                        uint64_t lane_bits, uint64_t block_bits, float* s_T,
-                                        float* s_w, float u, int lane) {
+__device__ __forceinline__ int r64_pick(const float* __restrict__ mat, int records, int row,
+                                        int ld, int n, int np, uint64_t lane_bits,
+                                        uint64_t block_bits, float* s_T, float* s_w, float u,
+                                        int lane) {
     u32x4 wa[P], wb[P];
-    load_row<G, P, GUARD, SKIP>(row, n, np, lane_bits, lane, wa, wb);
+    load_row<G, P, GUARD, SKIP>(mat, records, row, ld, np, lane_bits, lane, wa, wb);
     return pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, block_bits, s_T, s_w, u, lane);
 }
 
@@ -208,6 +215,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     const int lane = threadIdx.x;
     const int n = c.n;
     const int np = GUARD ? (n + Tile<G>::kPass - 1) / Tile<G>::kPass : P;
+    const int records = n * c.ld * 4;  // the whole n x ld choice matrix
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
     uint64_t block_bits = initial_block_bits(n, lane);
@@ -230,8 +238,8 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     if (LOAD_FIRST) {
         for (int step = 1; step < n; ++step) {
             u32x4 wa[P], wb[P];
-            load_row<G, P, GUARD, SKIP>(c.choice + (size_t)cur * c.ld, n, np, lane_bits, lane,
-                                        wa, wb);
+            load_row<G, P, GUARD, SKIP>(c.choice, records, cur, c.ld, np, lane_bits, lane, wa,
+                                        wb);
             if (lane == 0) s_tour[step - 1] = (uint16_t)cur;
             mark_visited<G>(cur, lane, lane_bits, block_bits);
             const int slot = (step - 1) & 63;
@@ -253,7 +261,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
             if (__builtin_expect(slot == 0, 0))
                 u64 = draws64(key, iter, (uint32_t)k, step, lane);
             const float u = read_lane(u64, slot);
-            const int j = r64_pick<G, P, GUARD, SKIP>(c.choice + (size_t)cur * c.ld, n, np,
+            const int j = r64_pick<G, P, GUARD, SKIP>(c.choice, records, cur, c.ld, n, np,
                                                       lane_bits, block_bits, sh.T, sh.w, u, lane);
             cur = j < 0 ? 0 : j;
         }
@@ -341,8 +349,10 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
             if (j < n && f[j]) lane_bits |= 1ull << (p * G + e);
         }
     __syncthreads();
-    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, n, P, lane_bits, vis, sh.T,
-                                              sh.w, us[q], lane);
+    // one row per query: the span is that row's n cities (rounded up to whole
+    // 16-byte loads; the caller's padding columns are zero)
+    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld, n,
+                                              P, lane_bits, vis, sh.T, sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
 

@@ -53,17 +53,22 @@ __device__ __forceinline__ void mark_visited_split(int j, int wv, int lane, uint
 // One R64 draw by the W waves of the workgroup over a row loaded with
 // load_split; s_T and s_w are this step's buffers.  Returns the chosen city
 // (the same in every wave), or -1 if no city is feasible.
+// The wave's passes of row `row` of the ld-padded matrix `mat`, through a
+// descriptor spanning `records` bytes and the scalar row offset, as in the
+// single-wave kernel (past the span: zeros; past n inside it: masked).
 template <int G, int W, int PW>
-__device__ __forceinline__ void load_split(const float* __restrict__ row, int n, int np, int wv,
-                                           int lane, u32x4 (&wa)[PW], u32x4 (&wb)[PW]) {
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, ((n + 3) & ~3) * 4);
+__device__ __forceinline__ void load_split(const float* __restrict__ mat, int records, int row,
+                                           int ld, int np, int wv, int lane, u32x4 (&wa)[PW],
+                                           u32x4 (&wb)[PW]) {
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(mat, records);
+    const int soff = row * ld * 4;
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
         const int p = wv + W * q;
         if (p >= np) break;
         const int off = (p * Tile<G>::kPass + lane * G) * 4;
-        wa[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-        if (G == 8) wb[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        wa[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, soff, 0);
+        if (G == 8) wb[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, soff, 0);
     }
 }
 
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(64 * W) void k_construct_split(Colony c, uint32_t i
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
         u32x4 wa[PW], wb[PW];
-        load_split<G, W, PW>(c.choice + (size_t)cur * c.ld, n, np, wv, lane, wa, wb);
+        load_split<G, W, PW>(c.choice, n * c.ld * 4, cur, c.ld, np, wv, lane, wa, wb);
         if (tid == 0) s_tour[step - 1] = (uint16_t)cur;
         mark_visited_split<G, W>(cur, wv, lane, lane_bits, block_bits);
         const int slot = (step - 1) & 63;
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(64 * W) void k_test_select_split(const float* rows,
     if (tid < 64) sh.T[0][lane] = 0.0f;
     __syncthreads();
     u32x4 wa[PW], wb[PW];
-    load_split<G, W, PW>(rows + (size_t)q * ld, n, np, wv, lane, wa, wb);
+    load_split<G, W, PW>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld, np, wv, lane, wa, wb);
     const int j = pick_split<G, W, PW>(wa, wb, n, np, wv, lane_bits, vis, sh.T[0], sh.w[0],
                                        us[q], lane);
     if (tid == 0) out[q] = j;

@@ -48,12 +48,12 @@ __device__ __forceinline__ int pick_fallback(uint64_t block_bits) {
     return b * 64 + 63 - __builtin_clzll(~lane_u64(block_bits, b));
 }
 
-// Buffer view of one choice row: loads at or beyond `valid_bytes` return 0
-// without touching memory.  valid_bytes is n rounded up to 4 cities, so a
-// 16-byte load is either wholly inside or wholly outside the row; the padding
-// columns between n and that bound hold zeros.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int valid_bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), (short)0, valid_bytes,
+// Buffer view of `bytes` bytes from `base`: a load whose scalar plus vector
+// offset is at or beyond it returns 0 without touching memory.  Every span
+// used is a multiple of 16 bytes, so a 16-byte load is wholly inside or
+// wholly outside it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, bytes,
                                              0x00020000);
 }
 
