@@ -94,6 +94,19 @@ __device__ __forceinline__ float s64_scan_row0(float x) {
     return x;
 }
 
+// The first L levels of stage A (L = 1..4).  On lanes 0 .. 2^L - 1 of
+// non-negative values this equals s64_scan_row0: the later levels would add
+// +0 there (their source lane is below 0), which changes no value >= +0.
+template <int L>
+__device__ __forceinline__ float s64_scan_row0_levels(float x) {
+    static_assert(L >= 1 && L <= 4, "one to four levels");
+    x = x + dpp_move<0x111, 0xF>(x);
+    if (L >= 2) x = x + dpp_move<0x112, 0xF>(x);
+    if (L >= 3) x = x + dpp_move<0x114, 0xF>(x);
+    if (L >= 4) x = x + dpp_move<0x118, 0xF>(x);
+    return x;
+}
+
 // Lane l receives lane l-1's value, lane 0 receives +0.
 __device__ __forceinline__ float wave_shift_up1(float x) { return dpp_move<0x138, 0xF>(x); }
 

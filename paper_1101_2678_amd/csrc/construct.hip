@@ -157,9 +157,14 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
         if ((lane % LPB) == LPB - 1) s_T[p * G + lane / LPB] = t;
     }
     // Rows of at most 1024 cities have nb <= 16 blocks, all in row 0 of the
-    // block-total scan, which stage B leaves as it is.
+    // block-total scan, which stage B leaves as it is; rows of at most 2^L
+    // blocks need only its first L levels.
     const float T = s_T[lane];
-    const float I = kAll ? s64_scan_row0(T) : s64_scan(T);
+    float I;
+    if constexpr (kAll)
+        I = s64_scan_row0_levels<block_scan_levels(P * G)>(T);
+    else
+        I = s64_scan(T);
     const float total = read_lane(I, nb - 1);
     const float target = u * total;
     const float E = wave_shift_up1(I);

@@ -170,7 +170,9 @@ struct ArrayDraws {
     }
 };
 
-// All ones if bit e of `bits` is set, else 0 (one v_bfe_i32).
+// All ones if bit e of `bits` is set, else 0 (one v_bfe_i32).  Inline
+// assembly here: through the builtin the compiler scheduled this kernel 3.5%
+// slower (n = 2400), while the roulette kernels gained from it.
 __device__ __forceinline__ uint32_t bit_mask(uint32_t bits, int e) {
     uint32_t m;
     asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(bits), "i"(e));

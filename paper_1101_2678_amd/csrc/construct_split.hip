@@ -101,7 +101,7 @@ __device__ __forceinline__ int pick_split(u32x4 (&wa)[PW], u32x4 (&wb)[PW], int 
     // n <= 1024: at most 16 blocks, all in row 0 of the block-total scan.
     const int nb = (n + 63) >> 6;
     const float T = s_T[lane];
-    const float I = s64_scan_row0(T);
+    const float I = s64_scan_row0_levels<block_scan_levels(W * PW * G)>(T);
     const float total = read_lane(I, nb - 1);
     const float target = u * total;
     const float E = wave_shift_up1(I);

@@ -39,6 +39,12 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Scan levels that cover the block totals of a row of at most `blocks`
+// 64-city blocks (at most 16: the blocks sit in row 0 of the scan).
+constexpr int block_scan_levels(int blocks) {
+    return blocks <= 2 ? 1 : blocks <= 4 ? 2 : blocks <= 8 ? 3 : 4;
+}
+
 // No prefix exceeds the target (rounding, or every weight zero): the highest
 // feasible city, or -1 if there is none.
 __device__ __forceinline__ int pick_fallback(uint64_t block_bits) {
@@ -57,13 +63,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* base, in
                                              0x00020000);
 }
 
-// Sign-extended bit `e` of `bits` (0 or all ones).  Written as v_bfe_i32 so
-// the masking of one city costs two VALU operations (extract, and).
+// Sign-extended bit `e` of `bits` (0 or all ones): one v_bfe_i32, so the
+// masking of one city costs two VALU operations (extract, and).  Through the
+// builtin rather than inline assembly, so the compiler sees the dependences
+// and can extract every mask before the row's loads return.
 template <int E>
 __device__ __forceinline__ uint32_t bit_mask(uint32_t bits) {
-    uint32_t m;
-    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(bits), "i"(E));
-    return m;
+    return (uint32_t)__builtin_amdgcn_sbfe((int)bits, E, 1);
 }
 
 template <int E0>
