@@ -293,6 +293,32 @@ def random_rows_rate(torch, aco, n: int, m: int, rows: int) -> float:
     return round(4.0 * n * m * (n - 1) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
 
 
+def random_rows_ceiling(torch, aco, n: int, m: int, waves_factors=(1, 4, 8)) -> dict:
+    """Best rate of reading random whole rows of an n x ld matrix (the choice
+    matrix's footprint) with m, 4m and 8m one-wave workgroups: the memory
+    system's limit for this access pattern, where each XCD's L2 keeps a share
+    of the rows (a sequential sweep of the footprint keeps none), measured
+    with up to eight times the wavefronts construction has in flight."""
+    stream = torch.cuda.current_stream()
+    ld = (n + 63) // 64 * 64
+    sink = torch.zeros(max(8 * m, 4096), dtype=torch.float32, device="cuda")
+    mat = torch.rand(n * ld, dtype=torch.float32, device="cuda")
+    by = {}
+    for f in waves_factors:
+        waves = f * m
+        steps = max(16, m * (n - 1) // (2 * waves))
+        aco.probe_rows(mat, n, ld, n, waves, 4, sink)
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        aco.probe_rows(mat, n, ld, n, waves, steps, sink)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        by[waves] = round(4.0 * n * waves * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del mat
+    best = max(by, key=by.get)
+    return {"GBps": by[best], "waves": best, "by_waves_GBps": by}
+
+
 def requested_bytes(tours: np.ndarray, n: int, skip: bool) -> int:
     """Bytes the construction kernel asks the memory system for in one launch
     (16-byte loads of 4-city groups).  With the skip path a group is loaded
@@ -752,25 +778,41 @@ def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool)
     req = requested_bytes(tours, n, skip=passes >= 3)
     foot = n * ld * 4
     ceil = stream_read_ceiling(torch, aco, foot)
+    rows_ceil = random_rows_ceiling(torch, aco, n, m)
+    peak = max(ceil["GBps"], rows_ceil["GBps"])
     roofline = {"bound": "mall" if foot > (4 << 20) else "l2", "achieved": round(achieved, 1),
-                "peak": ceil["GBps"], "unit": "GB/s", "frac": round(achieved / ceil["GBps"], 4),
+                "peak": peak, "unit": "GB/s", "frac": round(achieved / peak, 4),
                 "traffic": None, "kernel": f"k_construct<{tile},{passes}>",
                 "algorithmic_bytes_per_launch": alg,
-                "peak_note": (f"measured: streaming read of a {foot / 1e6:.1f} MB buffer (the "
-                              f"choice matrix's footprint), every XCD walking all of it, best of "
-                              f"{len(PROBE_SHAPES)} load shapes (aco_probe_read_shape: "
+                "peak_note": (f"measured at the choice matrix's {foot / 1e6:.1f} MB footprint, "
+                              f"the better of two reads of it: a streaming read, every XCD "
+                              f"walking all of it, best of {len(PROBE_SHAPES)} load shapes "
+                              f"(aco_probe_read_shape: {ceil['GBps']} GB/s with "
                               f"{ceil['loads_in_flight']} loads in flight"
                               f"{', nontemporal' if ceil['nontemporal'] else ''}, "
-                              f"{ceil['reps']} passes, {ceil['ms']} ms)"),
+                              f"{ceil['reps']} passes, {ceil['ms']} ms), and random whole rows "
+                              f"with 1, 4 and 8 times the kernel's {m} wavefronts "
+                              f"(aco_probe_rows: {rows_ceil['GBps']} GB/s with "
+                              f"{rows_ceil['waves']}), where each XCD's L2 keeps a share of the "
+                              f"rows as it does for the kernel"),
+                "peak_stream_GBps": ceil["GBps"],
                 "peak_by_shape_GBps": ceil["by_shape_GBps"],
+                "peak_random_rows_GBps": rows_ceil["GBps"],
+                "peak_random_rows_by_waves_GBps": rows_ceil["by_waves_GBps"],
                 "hbm_peak": HBM_PEAK_GBPS, "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBPS, 4),
                 "requested_bytes_per_launch": req,
                 "requested_GBps": round(req / (con_ms * 1e-3) / 1e9, 1),
-                "frac_requested": round(req / (con_ms * 1e-3) / 1e9 / ceil["GBps"], 4)}
+                "frac_requested": round(req / (con_ms * 1e-3) / 1e9 / peak, 4)}
     if main:
         traffic, traffic_note = traffic_from_profile()
         roofline["traffic"] = traffic
         roofline["traffic_note"] = traffic_note
+        if traffic:
+            # the bytes that crossed from the Infinity Cache / HBM side, against
+            # the sweep, which the L2 does not filter either
+            tr = traffic / (con_ms * 1e-3) / 1e9
+            roofline["traffic_GBps"] = round(tr, 1)
+            roofline["frac_traffic_of_stream"] = round(tr / ceil["GBps"], 4)
 
     upd = {}
     for kind, ms in t_upd_v.items():
