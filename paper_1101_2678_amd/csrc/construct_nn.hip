@@ -197,10 +197,6 @@ __global__ __launch_bounds__(64) void k_construct_nn(Colony c, NnTables t, uint3
 
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
     int cur = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
-    if (lane == 0) {
-        s_tour[0] = (uint16_t)cur;
-        s_vis[cur] = 1;
-    }
 
     // Lanes kp..63 re-read entries of the same row (kp is 32 or 64), so the
     // load needs no branch; only lanes < nn can be candidates.
@@ -211,16 +207,23 @@ __global__ __launch_bounds__(64) void k_construct_nn(Colony c, NnTables t, uint3
     // between the selected city and the next load (every access is in range)
     const __amdgpu_buffer_rsrc_t crs = __builtin_amdgcn_make_buffer_rsrc(
         t.cand, (short)0, n * kp * (int)sizeof(uint64_t), 0x00020000);
+    // A step's candidate row is loaded as soon as its city is known; the
+    // city's bookkeeping (tour entry, visited flag) follows the load, before
+    // the flags are read (one wavefront: its LDS accesses stay in order).
     float u64 = 0.0f;
     for (int step = 1; step < n; ++step) {
-        const int slot = (step - 1) & 63;
-        if (slot == 0)
-            u64 = uniform24(draw(key, iter, (uint32_t)k, (uint32_t)(step + lane)));
-        const float u = read_lane(u64, slot);
-
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
         const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(
             crs, col * (int)sizeof(uint64_t), cur * kp * (int)sizeof(uint64_t), 0);
+        if (lane == 0) {
+            s_tour[step - 1] = (uint16_t)cur;
+            s_vis[cur] = 1;
+        }
+        const int slot = (step - 1) & 63;
+        if (__builtin_expect(slot == 0, 0))
+            u64 = uniform24(draw(key, iter, (uint32_t)k, (uint32_t)(step + lane)));
+        const float u = read_lane(u64, slot);
+
         const int city = (int)v.y;
         // every lane reads its flag (a valid index on every lane), so the
         // read needs no branch; `&` keeps it unconditional
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(64) void k_construct_nn(Colony c, NnTables t, uint3
         const float target = u * read_lane(s, kNn32 ? 31 : 63);
         const uint64_t live = ballot(unvisited) & list_mask;
         int next;
-        if (live) {
+        if (__builtin_expect(live != 0, 1)) {
             const uint64_t hit = ballot(s > target) & live;
             const int r = hit ? __builtin_ctzll(hit) : 63 - __builtin_clzll(live);
             next = __builtin_amdgcn_readlane(city, r);
@@ -241,12 +244,9 @@ __global__ __launch_bounds__(64) void k_construct_nn(Colony c, NnTables t, uint3
             // keeps the LDS indices in range should that ever break.
             next = next < 0 ? 0 : next;
         }
-        if (lane == 0) {
-            s_tour[step] = (uint16_t)next;
-            s_vis[next] = 1;
-        }
         cur = next;
     }
+    if (lane == 0) s_tour[n - 1] = (uint16_t)cur;
     __syncthreads();
     if (lane == 0) s_tour[n] = s_tour[0];
     __syncthreads();
