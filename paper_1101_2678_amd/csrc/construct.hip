@@ -38,7 +38,7 @@ namespace {
 constexpr int kSkipOffset = 1 << 30;  // past any row: a buffer load there returns 0
 
 // Per-lane feasibility bits: bit G p + e <=> city 64 G p + G lane + e is < n
-// and not yet visited.  Passes at or beyond np stay empty.
+// and not yet visited.
 template <int G, int P>
 __device__ __forceinline__ uint64_t initial_lane_bits(int n, int lane) {
     uint64_t bits = 0;
@@ -88,7 +88,7 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
 }
 
 // Issues the loads of row `row` of the ld-padded matrix `mat` into wa/wb:
-// in pass p < np lane l takes cities 64Gp + Gl .. + G - 1.  The descriptor
+// in pass p lane l takes cities 64Gp + Gl .. + G - 1.  The descriptor
 // spans `records` bytes from mat and stays the same for the whole tour; the
 // row is selected by the scalar offset (two scalar operations per step), and
 // the range check covers scalar plus vector offset.  Loads past the end of
@@ -96,15 +96,14 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
 // cities but inside the span read padding or the next row, and masking
 // (whose bits exist only for cities < n) zeroes them.  With SKIP, a 16-byte
 // load whose four cities are all visited goes out of range instead.
-template <int G, int P, bool GUARD, bool SKIP>
+template <int G, int P, bool SKIP>
 __device__ __forceinline__ void load_row(const float* __restrict__ mat, int records, int row,
-                                         int ld, int np, uint64_t lane_bits, int lane,
-                                         u32x4 (&wa)[P], u32x4 (&wb)[P]) {
+                                         int ld, uint64_t lane_bits, int lane, u32x4 (&wa)[P],
+                                         u32x4 (&wb)[P]) {
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(mat, records);
     const int soff = row * ld * 4;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        if (GUARD && p >= np) break;
         const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
         const int off = (p * Tile<G>::kPass + lane * G) * 4;
         const int oa = (!SKIP || (bits & 0xFu)) ? off : kSkipOffset;
@@ -123,14 +122,14 @@ __device__ __forceinline__ void load_row(const float* __restrict__ mat, int reco
 template <int G, int P>
 constexpr bool kWriteAllPasses = (P * Tile<G>::kPass <= 1024);
 
-// One R64 roulette draw over a loaded row (wa/wb as load_row leaves them;
-// masked in place), with np <= P passes in use (np == P when GUARD is
-// false).  block_bits: the visited bits of block b in lane b.  Returns the
+// One R64 roulette draw over a loaded row of P passes (wa/wb as load_row
+// leaves them; masked in place).  block_bits: the visited bits of block b in
+// lane b.  Returns the
 // chosen city, or -1 if no city is feasible.  Wave-uniform.  The workgroup is
 // one wavefront: its LDS operations execute in program order, and every LDS
 // access below uses a lane-dependent index, so the compiler keeps the order.
-template <int G, int P, bool GUARD>
-__device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n, int np,
+template <int G, int P>
+__device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n,
                                            uint64_t lane_bits, uint64_t block_bits, float* s_T,
                                            float* s_w, float u, int lane) {
     constexpr int LPB = Tile<G>::kLanesPerBlock;
@@ -138,7 +137,6 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
     const int nb = (n + 63) >> 6;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        if (GUARD && p >= np) break;
         const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
         mask4<0>(wa[p], bits);
         float t;
@@ -196,14 +194,13 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
     return pick_fallback(block_bits);
 }
 
-template <int G, int P, bool GUARD, bool SKIP>
+template <int G, int P, bool SKIP>
 __device__ __forceinline__ int r64_pick(const float* __restrict__ mat, int records, int row,
-                                        int ld, int n, int np, uint64_t lane_bits,
-                                        uint64_t block_bits, float* s_T, float* s_w, float u,
-                                        int lane) {
+                                        int ld, int n, uint64_t lane_bits, uint64_t block_bits,
+                                        float* s_T, float* s_w, float u, int lane) {
     u32x4 wa[P], wb[P];
-    load_row<G, P, GUARD, SKIP>(mat, records, row, ld, np, lane_bits, lane, wa, wb);
-    return pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, block_bits, s_T, s_w, u, lane);
+    load_row<G, P, SKIP>(mat, records, row, ld, lane_bits, lane, wa, wb);
+    return pick_loaded<G, P>(wa, wb, n, lane_bits, block_bits, s_T, s_w, u, lane);
 }
 
 // LDS a construction workgroup needs besides the tour.
@@ -214,12 +211,11 @@ struct AntShared {
 
 // The whole tour of ant k of colony c in iteration `iter`: placement, n - 1
 // roulette steps, then length, deposit, tour and neighbour tables.
-template <int G, int P, bool GUARD, bool SKIP, bool LOAD_FIRST>
+template <int G, int P, bool SKIP, bool LOAD_FIRST>
 __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t iter,
                                               uint16_t* s_tour, AntShared& sh) {
     const int lane = threadIdx.x;
     const int n = c.n;
-    const int np = GUARD ? (n + Tile<G>::kPass - 1) / Tile<G>::kPass : P;
     const int records = n * c.ld * 4;  // the whole n x ld choice matrix
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
@@ -243,16 +239,15 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     if (LOAD_FIRST) {
         for (int step = 1; step < n; ++step) {
             u32x4 wa[P], wb[P];
-            load_row<G, P, GUARD, SKIP>(c.choice, records, cur, c.ld, np, lane_bits, lane, wa,
-                                        wb);
+            load_row<G, P, SKIP>(c.choice, records, cur, c.ld, lane_bits, lane, wa, wb);
             if (lane == 0) s_tour[step - 1] = (uint16_t)cur;
             mark_visited<G>(cur, lane, lane_bits, block_bits);
             const int slot = (step - 1) & 63;
             if (__builtin_expect(slot == 0, 0))
                 u64 = draws64(key, iter, (uint32_t)k, step, lane);
             const float u = read_lane(u64, slot);
-            const int j = pick_loaded<G, P, GUARD>(wa, wb, n, np, lane_bits, block_bits, sh.T,
-                                                   sh.w, u, lane);
+            const int j = pick_loaded<G, P>(wa, wb, n, lane_bits, block_bits, sh.T, sh.w, u,
+                                            lane);
             // At every step n - step >= 1 cities are unvisited, so j >= 0;
             // the clamp only keeps the LDS indices in range should that
             // ever break.
@@ -266,8 +261,8 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
             if (__builtin_expect(slot == 0, 0))
                 u64 = draws64(key, iter, (uint32_t)k, step, lane);
             const float u = read_lane(u64, slot);
-            const int j = r64_pick<G, P, GUARD, SKIP>(c.choice, records, cur, c.ld, n, np,
-                                                      lane_bits, block_bits, sh.T, sh.w, u, lane);
+            const int j = r64_pick<G, P, SKIP>(c.choice, records, cur, c.ld, n, lane_bits,
+                                               block_bits, sh.T, sh.w, u, lane);
             cur = j < 0 ? 0 : j;
         }
     }
@@ -298,19 +293,35 @@ template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
     __shared__ __align__(16) AntShared sh;
-    construct_ant<G, P, false, (P >= 3), (P < 3)>(c, ant_of_block(blockIdx.x, c.m), iter,
-                                                  s_tour, sh);
+    construct_ant<G, P, (P >= 3), (P < 3)>(c, ant_of_block(blockIdx.x, c.m), iter, s_tour, sh);
 }
 
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
 // cols[antmap[g] >> 16] in that colony's current iteration (*iter_dev).  Each
-// colony carries its own tile; the pass count is read at run time (GUARD).
-// P8 bounds the passes of tile-8 colonies (every colony of the launch has
-// n <= 512 P8), so a batch of small instances holds no registers for rows it
-// does not have; tile 4 is only ever set for n <= 1024 (4 passes).
+// colony carries its own tile, and its pass count picks the ant's code
+// (batch_ant).  P8 bounds the passes of tile-8 colonies (every colony of the
+// launch has n <= 512 P8), so a batch of small instances holds no registers
+// for rows it does not have; tile 4 is only ever set for n <= 1024 (4
+// passes).
 // Loads first in the batched launch too: 754 -> 761 solves/s on the
 // 256-instance workload (n 50..1000, same box).
 constexpr bool kBatchLoadFirst = true;
+
+// The ant's code for its colony's exact pass count NP (1 .. PMAX): each
+// instance runs a loop specialised for its row length, with no per-pass
+// test of the pass count inside the step (256 instances, n 50..1000: 757 ->
+// 762 solves/s against one loop with run-time pass tests).
+template <int G, int NP, int PMAX>
+__device__ __forceinline__ void batch_ant(const Colony& c, int k, uint32_t iter, int np,
+                                          uint16_t* s_tour, AntShared& sh) {
+    if constexpr (NP < PMAX) {
+        if (np != NP) {
+            batch_ant<G, NP + 1, PMAX>(c, k, iter, np, s_tour, sh);
+            return;
+        }
+    }
+    construct_ant<G, NP, true, kBatchLoadFirst>(c, k, iter, s_tour, sh);
+}
 
 template <int P8>
 __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict__ cols,
@@ -324,11 +335,14 @@ __global__ __launch_bounds__(64) void k_construct_batch(const Colony* __restrict
     // start city and every row address of the tour, each load of which then
     // becomes a loop over lanes.
     const uint32_t iter = __builtin_amdgcn_readfirstlane(*c.iter_dev);
-    if (c.tile == 4)
-        construct_ant<4, 4, true, true, kBatchLoadFirst>(c, (int)(e & 0xffffu), iter, s_tour, sh);
-    else
-        construct_ant<8, P8, true, true, kBatchLoadFirst>(c, (int)(e & 0xffffu), iter, s_tour,
-                                                          sh);
+    const int k = (int)(e & 0xffffu);
+    if (c.tile == 4) {
+        const int np = __builtin_amdgcn_readfirstlane((c.n + 255) / 256);
+        batch_ant<4, 1, 4>(c, k, iter, np, s_tour, sh);
+    } else {
+        const int np = __builtin_amdgcn_readfirstlane((c.n + 511) / 512);
+        batch_ant<8, 1, P8>(c, k, iter, np, s_tour, sh);
+    }
 }
 
 template <int G, int P>
@@ -356,8 +370,8 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
     __syncthreads();
     // one row per query: the span is that row's n cities (rounded up to whole
     // 16-byte loads; the caller's padding columns are zero)
-    const int j = r64_pick<G, P, false, true>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld, n,
-                                              P, lane_bits, vis, sh.T, sh.w, us[q], lane);
+    const int j = r64_pick<G, P, true>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld, n,
+                                       lane_bits, vis, sh.T, sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }
 
