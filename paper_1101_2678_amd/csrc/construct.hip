@@ -124,10 +124,10 @@ constexpr bool kWriteAllPasses = (P * Tile<G>::kPass <= 1024);
 
 // One R64 roulette draw over a loaded row of P passes (wa/wb as load_row
 // leaves them; masked in place).  block_bits: the visited bits of block b in
-// lane b.  Returns the
-// chosen city, or -1 if no city is feasible.  Wave-uniform.  The workgroup is
-// one wavefront: its LDS operations execute in program order, and every LDS
-// access below uses a lane-dependent index, so the compiler keeps the order.
+// lane b.  Returns the chosen city, or -1 if no city is feasible.
+// Wave-uniform.  The workgroup is one wavefront: its LDS operations execute
+// in program order, and every LDS access below uses a lane-dependent index,
+// so the compiler keeps the order.
 template <int G, int P>
 __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n,
                                            uint64_t lane_bits, uint64_t block_bits, float* s_T,
