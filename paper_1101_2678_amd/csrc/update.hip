@@ -93,14 +93,33 @@ __device__ __forceinline__ void best_of(const Colony& c, bool advance_iter) {
     if (advance_iter && tid == 0) *c.iter_dev += 1u;
 }
 
-// Row i of the gather update (tid in [0, kRowThreads)).
+// Row i of the gather update by a workgroup of T threads.  The deposits go
+// four ants at a time (one 8-byte load of four successors, one of four
+// predecessors, one 16-byte load of four deposits), the row's accumulators
+// are cleared 16 bytes at a time.
+template <int T>
 __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) {
     const int tid = threadIdx.x;
-    for (int j = tid; j < c.ld; j += kRowThreads) s_D[j] = 0.0;
+    double2* s_D2 = reinterpret_cast<double2*>(s_D);
+    for (int j = tid; j < c.ld / 2; j += T) s_D2[j] = make_double2(0.0, 0.0);
     __syncthreads();
     const uint16_t* sr = c.succ + (size_t)i * c.mp;
     const uint16_t* pr = c.pred + (size_t)i * c.mp;
-    for (int k = tid; k < c.m; k += kRowThreads) {
+    const int m4 = c.m / 4;
+    for (int q = tid; q < m4; q += T) {
+        const ushort4 su = reinterpret_cast<const ushort4*>(sr)[q];
+        const ushort4 pu = reinterpret_cast<const ushort4*>(pr)[q];
+        const float4 dv = reinterpret_cast<const float4*>(c.dep)[q];
+        unsafeAtomicAdd(&s_D[su.x], (double)dv.x);
+        unsafeAtomicAdd(&s_D[pu.x], (double)dv.x);
+        unsafeAtomicAdd(&s_D[su.y], (double)dv.y);
+        unsafeAtomicAdd(&s_D[pu.y], (double)dv.y);
+        unsafeAtomicAdd(&s_D[su.z], (double)dv.z);
+        unsafeAtomicAdd(&s_D[pu.z], (double)dv.z);
+        unsafeAtomicAdd(&s_D[su.w], (double)dv.w);
+        unsafeAtomicAdd(&s_D[pu.w], (double)dv.w);
+    }
+    for (int k = 4 * m4 + tid; k < c.m; k += T) {
         const double d = (double)c.dep[k];
         unsafeAtomicAdd(&s_D[sr[k]], d);
         unsafeAtomicAdd(&s_D[pr[k]], d);
@@ -110,7 +129,7 @@ __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) 
     float4* trow = reinterpret_cast<float4*>(c.tau + (size_t)i * c.ld);
     float4* crow = reinterpret_cast<float4*>(c.choice + (size_t)i * c.ld);
     const int4* drow = reinterpret_cast<const int4*>(c.dist + (size_t)i * c.ld);
-    for (int q = tid; q < c.ld / 4; q += kRowThreads) {
+    for (int q = tid; q < c.ld / 4; q += T) {
         float4 t = trow[q];
         const int4 d = drow[q];
         float4 ch;
@@ -123,23 +142,30 @@ __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) 
     }
 }
 
+// Threads per row of the single-instance gather update.  Each row's
+// accumulators take ld binary64 words of LDS, which caps the rows a compute
+// unit holds (8 at n = 2400, 2048 on the device for 2400 rows); more threads
+// per row shorten each row, so the rows that do not fit the first round cost
+// less.
+constexpr int kGatherThreads = 256;
+
 // Workgroup 0 also keeps the best-so-far tour (it reads only the lengths and
 // tours of the construction, which the update does not touch), so one launch
 // serves both.
-__global__ __launch_bounds__(kRowThreads) void k_update_gather(Colony c) {
-    extern __shared__ double s_D[];  // ld binary64 accumulators
-    if (blockIdx.x == 0) best_of<kRowThreads>(c, false);
-    gather_row(c, blockIdx.x, s_D);
+__global__ __launch_bounds__(kGatherThreads) void k_update_gather(Colony c) {
+    extern __shared__ __align__(16) double s_D[];  // ld binary64 accumulators
+    if (blockIdx.x == 0) best_of<kGatherThreads>(c, false);
+    gather_row<kGatherThreads>(c, blockIdx.x, s_D);
 }
 
 // Batched gather: workgroup g updates row (rowmap[g] & 0xffff) of colony
 // cols[rowmap[g] >> 16].
 __global__ __launch_bounds__(kRowThreads) void k_update_gather_batch(
     const Colony* __restrict__ cols, const uint32_t* __restrict__ rowmap) {
-    extern __shared__ double s_D[];
+    extern __shared__ __align__(16) double s_D[];
     const uint32_t e = rowmap[blockIdx.x];
     const Colony c = cols[e >> 16];
-    gather_row(c, (int)(e & 0xffffu), s_D);
+    gather_row<kRowThreads>(c, (int)(e & 0xffffu), s_D);
 }
 
 // grid (ceil(n / 256), m): thread (s, k) adds ant k's deposit for the tour
@@ -335,7 +361,7 @@ dim3 cell_grid(const Colony& c) { return dim3((c.ld / 4 + 255) / 256, c.n); }
 }  // namespace
 
 hipError_t launch_update_gather(const Colony& c, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_gather, dim3(c.n), dim3(kRowThreads),
+    hipLaunchKernelGGL(k_update_gather, dim3(c.n), dim3(kGatherThreads),
                        (size_t)c.ld * sizeof(double), s, c);
     return hipGetLastError();
 }
