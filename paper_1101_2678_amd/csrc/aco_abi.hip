@@ -106,7 +106,7 @@ Layout make_layout(const aco_params& p) {
 // in binary64 only if the deposits 1/C^k span few binades: with
 // LB <= C^k <= UB (each city contributes half of its two cheapest / two
 // dearest incident edges) we need bits(m) + bits(UB/LB) + 1 + 24 <= 53.
-bool dist_valid(const int32_t* d, int n, int m, std::string* why) {
+bool dist_valid(const int32_t* d, int n, int m, std::string* why, int* dep_emin) {
     double lb = 0.0, ub = 0.0;
     for (int i = 0; i < n; ++i) {
         if (d[(size_t)i * n + i] != 0) return (*why = "distance matrix diagonal must be 0", false);
@@ -127,11 +127,20 @@ bool dist_valid(const int32_t* d, int n, int m, std::string* why) {
     const int spread = (int)std::ceil(std::log2(ub / lb)) + 1;
     if (mbits + spread + 24 > 53)
         return (*why = "tour lengths span too many binades for exact binary64 deposit sums", false);
+    if (dep_emin) {
+        // every C^k <= UB, so every deposit fl32(1/C^k) >= fl32(1/UB): its
+        // exponent field bounds theirs from below (the fixed-point scale of
+        // the update's accumulators)
+        const float dmin = (float)(1.0 / ub);
+        uint32_t bits;
+        std::memcpy(&bits, &dmin, sizeof bits);
+        *dep_emin = (int)((bits >> 23) & 0xFFu);
+    }
     return true;
 }
 
-Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile,
-             int waves) {
+Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int dep_emin,
+             int tile, int waves) {
     Colony col{};
     col.n = p.n;
     col.m = p.m;
@@ -158,6 +167,7 @@ Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, 
     col.delta = with_delta ? reinterpret_cast<double*>(base + L.delta) : nullptr;
     col.tile = tile;
     col.waves = waves;
+    col.dep_emin = dep_emin;
     return col;
 }
 
@@ -321,7 +331,9 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     std::string why;
     if (!aco::host::params_valid(p, &why)) return fail(ACO_ERR_INVALID, why);
     if (!dist_host) return fail(ACO_ERR_INVALID, "dist_host is NULL");
-    if (!aco::host::dist_valid(dist_host, p->n, p->m, &why)) return fail(ACO_ERR_INVALID, why);
+    int dep_emin = 0;
+    if (!aco::host::dist_valid(dist_host, p->n, p->m, &why, &dep_emin))
+        return fail(ACO_ERR_INVALID, why);
     const aco::host::Layout L = aco::host::make_layout(*p);
     if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
         return fail(ACO_ERR_NOMEM, "workspace must be a 256-byte aligned device pointer");
@@ -338,7 +350,7 @@ aco_status aco_init(aco_ctx** out, const aco_params* p, const int32_t* dist_host
     c->device = device;
     c->scratch_err = aco::host::noalloc_scratch(device, &c->scratch);
     c->has_atomic = ws_bytes >= L.atomic_end;
-    c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic,
+    c->col = aco::host::carve(static_cast<char*>(d_workspace), L, *p, c->has_atomic, dep_emin,
                               aco::host::tile_for(p->n), aco::host::waves_for(p->n));
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->ws_bytes = ws_bytes;

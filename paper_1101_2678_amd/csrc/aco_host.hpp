@@ -31,10 +31,12 @@ size_t round_up(size_t v, size_t a);
 // runtime on `device`; otherwise the failure is recorded under `where`.
 aco_status stream_on_device(void* hip_stream, int device, const char* where);
 bool params_valid(const aco_params* p, std::string* why);
-bool dist_valid(const int32_t* d, int n, int m, std::string* why);
+// Checks the distances; dep_emin (may be NULL) receives a lower bound on the
+// binary32 exponent field of every deposit fl32(1/C^k) the instance can have.
+bool dist_valid(const int32_t* d, int n, int m, std::string* why, int* dep_emin = nullptr);
 Layout make_layout(const aco_params& p);
-Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int tile,
-             int waves = 1);
+Colony carve(char* base, const Layout& L, const aco_params& p, bool with_delta, int dep_emin,
+             int tile, int waves = 1);
 // Clears the colony's base arrays, uploads the distances and enqueues the
 // initialisation kernels (nearest-neighbour tour, tau0, tau and choice fill).
 hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t base_bytes,

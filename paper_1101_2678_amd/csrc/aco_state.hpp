@@ -33,6 +33,7 @@ struct Colony {
     uint32_t* iter_dev;  // next iteration (batched path; advanced on the device)
     int32_t tile;        // construction tile: cities per lane per pass (4 or 8)
     int32_t waves;       // construction wavefronts per ant (1, or 2 / 4 for n <= 1024)
+    int32_t dep_emin;    // every deposit fl32(1/C^k) has a binary32 exponent field >= this
 };
 
 constexpr int kMaxCities = 4096;

@@ -171,9 +171,10 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
     std::string why;
     if (!batch_layout(count, params, &B, &why)) return fail(ACO_ERR_INVALID, why);
     if (!dist_hosts) return fail(ACO_ERR_INVALID, "dist_hosts is NULL");
+    std::vector<int> dep_emin(count, 0);
     for (int q = 0; q < count; ++q) {
         if (!dist_hosts[q]) return fail(ACO_ERR_INVALID, "dist_hosts[" + std::to_string(q) + "] is NULL");
-        if (!aco::host::dist_valid(dist_hosts[q], params[q].n, params[q].m, &why))
+        if (!aco::host::dist_valid(dist_hosts[q], params[q].n, params[q].m, &why, &dep_emin[q]))
             return fail(ACO_ERR_INVALID, "instance " + std::to_string(q) + ": " + why);
     }
     if (!d_workspace || ((uintptr_t)d_workspace % aco::host::kAlign) != 0)
@@ -204,7 +205,7 @@ aco_status aco_batch_init(aco_batch** out, int32_t count, const aco_params* para
     hipError_t e = hipSuccess;
     for (int q = 0; q < count && e == hipSuccess; ++q) {
         b->cols[q] = aco::host::carve(base + B.inst_off[q], B.inst[q], params[q], false,
-                                      aco::host::tile_for(params[q].n));
+                                      dep_emin[q], aco::host::tile_for(params[q].n));
         e = aco::host::upload_and_init(b->cols[q], dist_hosts[q], B.inst[q].base_end, b->stream);
         b->max_n = std::max(b->max_n, params[q].n);
         b->max_ld = std::max(b->max_ld, B.inst[q].ld);
@@ -456,13 +457,18 @@ aco_status aco_autotune(void* d_workspace, size_t ws_bytes, const int32_t* sizes
         const aco_params p{n, n, 1, 2, 0.5f, 1};
         const aco::host::Layout L = aco::host::make_layout(p);
         const std::vector<int32_t> d = tuning_instance(n);
+        // construction only: the deposits' scale is not used, but is filled in
+        std::string why;
+        int dep_emin = 0;
+        (void)aco::host::dist_valid(d.data(), n, n, &why, &dep_emin);
         float t_best = 1e30f;
         for (int k = 0; k < ACO_NUM_SHAPES; ++k) {
             const int tile = kShapes[k][0], waves = kShapes[k][1];
             if (ms) ms[(size_t)i * ACO_NUM_SHAPES + k] = -1.0f;
             if (!aco::host::shape_supported(tile, waves, n)) continue;
             const aco::Colony col =
-                aco::host::carve(static_cast<char*>(d_workspace), L, p, false, tile, waves);
+                aco::host::carve(static_cast<char*>(d_workspace), L, p, false, dep_emin, tile,
+                                 waves);
             e = aco::host::upload_and_init(col, d.data(), L.base_end, s);
             if (e == hipSuccess) e = aco::launch_construct(col, 0, s);  // warm-up
             if (e == hipSuccess) e = hipEventRecord(e0, s);

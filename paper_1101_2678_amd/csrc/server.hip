@@ -255,7 +255,9 @@ aco_status aco_server_submit(aco_server* s, const aco_params* p, const int32_t* 
     if (!aco::host::params_valid(p, &why)) return fail(ACO_ERR_INVALID, why);
     if (!dist_host) return fail(ACO_ERR_INVALID, "dist_host is NULL");
     if (iters < 1) return fail(ACO_ERR_INVALID, "iters must be >= 1");
-    if (!aco::host::dist_valid(dist_host, p->n, p->m, &why)) return fail(ACO_ERR_INVALID, why);
+    int dep_emin = 0;
+    if (!aco::host::dist_valid(dist_host, p->n, p->m, &why, &dep_emin))
+        return fail(ACO_ERR_INVALID, why);
     const int cls = class_of(s, p->n);
     int free_slot = -1;
     int class_ants = 0, class_rows = 0;
@@ -274,7 +276,7 @@ aco_status aco_server_submit(aco_server* s, const aco_params* p, const int32_t* 
     size_t off = 0;
     if (!pool_alloc(s, L.base_end, &off)) return fail(ACO_ERR_NOMEM, "no free pool block large enough");
     Slot& sl = s->slots[free_slot];
-    sl.col = aco::host::carve(s->pool + off, L, *p, false, aco::host::tile_for(p->n));
+    sl.col = aco::host::carve(s->pool + off, L, *p, false, dep_emin, aco::host::tile_for(p->n));
     sl.off = off;
     sl.bytes = L.base_end;
     sl.iters_total = iters;

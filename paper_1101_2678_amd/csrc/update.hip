@@ -7,17 +7,23 @@
 // about 2 d_max and n d_max, n <= 4096) the sum needs fewer than 53 bits, so
 // it is exact in any order.  The evaporated value and that sum are then
 // added with a single rounding:  tau' = fl32((double)fl32(tau * keep) + D).
+// The same bound makes the sum exact in fixed point: scaled by 2^S, with S
+// such that the smallest deposit the instance can have is an integer, every
+// deposit is an integer and every sum an integer below 2^53, so the LDS
+// accumulators hold unsigned 64-bit integers (integer atomics, faster than
+// binary64 ones on this part) and convert back to the same binary64 value
+// exactly.
 //
 //   gather  (scatter-to-gather, Section III-B, without the O(n^4) scan): one
 //           workgroup owns row i, reads succ[i][*] and pred[i][*] (the two
 //           tour neighbours of city i in every ant's tour), accumulates the
-//           deposits in binary64 LDS slots, then evaporates, adds and
+//           deposits in 64-bit fixed-point LDS slots, then evaporates, adds and
 //           refreshes the choice row.  No global atomics.
 //   atomic  (Section III-B, "atomic instructions + shared memory", the
 //           paper's fastest update): one thread per city of an ant's tour.
 //           The threads of city i (the tours' edges leaving i, read from
-//           succ[i][*]) first add their deposits in binary64 LDS slots keyed
-//           by the edge's other end; each non-zero slot then goes to the
+//           succ[i][*]) first add their deposits in fixed-point LDS slots
+//           keyed by the edge's other end; each non-zero slot then goes to the
 //           upper-triangle cell of its undirected edge with one global
 //           binary64 atomic, which merges the two directions an edge can be
 //           travelled in.  An epilogue over pairs of 64 x 64 tiles
@@ -34,6 +40,23 @@ namespace aco {
 namespace {
 
 constexpr int kRowThreads = 256;
+
+// Fixed-point deposits.  c.dep_emin bounds the binary32 exponent field of
+// every deposit from below (from the instance's longest possible tour) and
+// fixes the scale 2^S, S = 150 - dep_emin: a deposit with exponent field e
+// and 24-bit significand M is M << (e - dep_emin), exactly, and a sum A
+// stands for A * 2^-S.  The bound on the tour lengths' spread that makes
+// binary64 sums exact keeps every sum of up to m deposits below 2^53, so A
+// converts back to binary64 exactly.
+__device__ __forceinline__ unsigned long long fixed_of(float d, int e_min) {
+    const uint32_t b = __float_as_uint(d);
+    const uint32_t sig = (b & 0x7FFFFFu) | 0x800000u;  // deposits are normal, > 0
+    return (unsigned long long)sig << (int)(((b >> 23) & 0xFFu) - (uint32_t)e_min);
+}
+
+__device__ __forceinline__ double value_of(unsigned long long a, int e_min) {
+    return ldexp((double)a, e_min - 150);
+}
 
 __device__ __forceinline__ float evaporation_keep(float rho) {
     return (float)(1.0 - (double)rho);  // fl32(1 - rho)
@@ -95,14 +118,15 @@ __device__ __forceinline__ void best_of(const Colony& c, bool advance_iter) {
 
 // Row i of the gather update by a workgroup of T threads.  The deposits go
 // four ants at a time (one 8-byte load of four successors, one of four
-// predecessors, one 16-byte load of four deposits), the row's accumulators
-// are cleared 16 bytes at a time.
+// predecessors, one 16-byte load of four deposits) into fixed-point LDS
+// accumulators, cleared 16 bytes at a time.
 template <int T>
-__device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) {
+__device__ __forceinline__ void gather_row(const Colony& c, int i, unsigned long long* s_A) {
     const int tid = threadIdx.x;
-    double2* s_D2 = reinterpret_cast<double2*>(s_D);
-    for (int j = tid; j < c.ld / 2; j += T) s_D2[j] = make_double2(0.0, 0.0);
+    ulonglong2* s_A2 = reinterpret_cast<ulonglong2*>(s_A);
+    for (int j = tid; j < c.ld / 2; j += T) s_A2[j] = make_ulonglong2(0ull, 0ull);
     __syncthreads();
+    const int e_min = c.dep_emin;
     const uint16_t* sr = c.succ + (size_t)i * c.mp;
     const uint16_t* pr = c.pred + (size_t)i * c.mp;
     const int m4 = c.m / 4;
@@ -110,19 +134,21 @@ __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) 
         const ushort4 su = reinterpret_cast<const ushort4*>(sr)[q];
         const ushort4 pu = reinterpret_cast<const ushort4*>(pr)[q];
         const float4 dv = reinterpret_cast<const float4*>(c.dep)[q];
-        unsafeAtomicAdd(&s_D[su.x], (double)dv.x);
-        unsafeAtomicAdd(&s_D[pu.x], (double)dv.x);
-        unsafeAtomicAdd(&s_D[su.y], (double)dv.y);
-        unsafeAtomicAdd(&s_D[pu.y], (double)dv.y);
-        unsafeAtomicAdd(&s_D[su.z], (double)dv.z);
-        unsafeAtomicAdd(&s_D[pu.z], (double)dv.z);
-        unsafeAtomicAdd(&s_D[su.w], (double)dv.w);
-        unsafeAtomicAdd(&s_D[pu.w], (double)dv.w);
+        const unsigned long long a = fixed_of(dv.x, e_min), b = fixed_of(dv.y, e_min);
+        const unsigned long long g = fixed_of(dv.z, e_min), h = fixed_of(dv.w, e_min);
+        atomicAdd(&s_A[su.x], a);
+        atomicAdd(&s_A[pu.x], a);
+        atomicAdd(&s_A[su.y], b);
+        atomicAdd(&s_A[pu.y], b);
+        atomicAdd(&s_A[su.z], g);
+        atomicAdd(&s_A[pu.z], g);
+        atomicAdd(&s_A[su.w], h);
+        atomicAdd(&s_A[pu.w], h);
     }
     for (int k = 4 * m4 + tid; k < c.m; k += T) {
-        const double d = (double)c.dep[k];
-        unsafeAtomicAdd(&s_D[sr[k]], d);
-        unsafeAtomicAdd(&s_D[pr[k]], d);
+        const unsigned long long a = fixed_of(c.dep[k], e_min);
+        atomicAdd(&s_A[sr[k]], a);
+        atomicAdd(&s_A[pr[k]], a);
     }
     __syncthreads();
     const float keep = evaporation_keep(c.rho);
@@ -133,17 +159,17 @@ __device__ __forceinline__ void gather_row(const Colony& c, int i, double* s_D) 
         float4 t = trow[q];
         const int4 d = drow[q];
         float4 ch;
-        apply_cell(t.x, ch.x, d.x, s_D[4 * q + 0], keep, c.alpha, c.beta);
-        apply_cell(t.y, ch.y, d.y, s_D[4 * q + 1], keep, c.alpha, c.beta);
-        apply_cell(t.z, ch.z, d.z, s_D[4 * q + 2], keep, c.alpha, c.beta);
-        apply_cell(t.w, ch.w, d.w, s_D[4 * q + 3], keep, c.alpha, c.beta);
+        apply_cell(t.x, ch.x, d.x, value_of(s_A[4 * q + 0], e_min), keep, c.alpha, c.beta);
+        apply_cell(t.y, ch.y, d.y, value_of(s_A[4 * q + 1], e_min), keep, c.alpha, c.beta);
+        apply_cell(t.z, ch.z, d.z, value_of(s_A[4 * q + 2], e_min), keep, c.alpha, c.beta);
+        apply_cell(t.w, ch.w, d.w, value_of(s_A[4 * q + 3], e_min), keep, c.alpha, c.beta);
         trow[q] = t;
         crow[q] = ch;
     }
 }
 
 // Threads per row of the single-instance gather update.  Each row's
-// accumulators take ld binary64 words of LDS, which caps the rows a compute
+// accumulators take ld 64-bit words of LDS, which caps the rows a compute
 // unit holds (8 at n = 2400, 2048 on the device for 2400 rows); more threads
 // per row shorten each row, so the rows that do not fit the first round cost
 // less.
@@ -153,19 +179,19 @@ constexpr int kGatherThreads = 256;
 // tours of the construction, which the update does not touch), so one launch
 // serves both.
 __global__ __launch_bounds__(kGatherThreads) void k_update_gather(Colony c) {
-    extern __shared__ __align__(16) double s_D[];  // ld binary64 accumulators
+    extern __shared__ __align__(16) unsigned long long s_A[];  // ld accumulators
     if (blockIdx.x == 0) best_of<kGatherThreads>(c, false);
-    gather_row<kGatherThreads>(c, blockIdx.x, s_D);
+    gather_row<kGatherThreads>(c, blockIdx.x, s_A);
 }
 
 // Batched gather: workgroup g updates row (rowmap[g] & 0xffff) of colony
 // cols[rowmap[g] >> 16].
 __global__ __launch_bounds__(kRowThreads) void k_update_gather_batch(
     const Colony* __restrict__ cols, const uint32_t* __restrict__ rowmap) {
-    extern __shared__ __align__(16) double s_D[];
+    extern __shared__ __align__(16) unsigned long long s_A[];
     const uint32_t e = rowmap[blockIdx.x];
     const Colony c = cols[e >> 16];
-    gather_row<kRowThreads>(c, (int)(e & 0xffffu), s_D);
+    gather_row<kRowThreads>(c, (int)(e & 0xffffu), s_A);
 }
 
 // grid (ceil(n / 256), m): thread (s, k) adds ant k's deposit for the tour
@@ -184,26 +210,28 @@ __global__ __launch_bounds__(256) void k_deposit_atomic(Colony c) {
 
 // grid (n, slices): workgroup (i, q) takes the ants k = q, q + slices, ...
 // (interleaved, so every slice reads whole contiguous runs of succ[i][*]).
-// Thread t adds dep_k for the edge i -> succ_k(i) into LDS slot succ_k(i);
-// the non-zero slots then go out as one global atomic each.  An ant's tour
-// holds an undirected edge at most once, so each deposit reaches its cell
-// exactly once, and the binary64 sums stay exact whatever the grouping.
+// Thread t adds dep_k for the edge i -> succ_k(i) into fixed-point LDS slot
+// succ_k(i); the non-zero slots then go out, converted back to binary64
+// (exactly), as one global atomic each.  An ant's tour holds an undirected
+// edge at most once, so each deposit reaches its cell exactly once, and the
+// sums stay exact whatever the grouping.
 __global__ __launch_bounds__(kRowThreads) void k_deposit_shared(Colony c) {
-    extern __shared__ double s_D[];  // ld binary64 slots, one per other end j
+    extern __shared__ __align__(16) unsigned long long s_A[];  // one slot per other end j
     const int i = blockIdx.x;
     const int tid = threadIdx.x;
-    for (int j = tid; j < c.ld; j += kRowThreads) s_D[j] = 0.0;
+    for (int j = tid; j < c.ld; j += kRowThreads) s_A[j] = 0ull;
     __syncthreads();
+    const int e_min = c.dep_emin;
     const uint16_t* sr = c.succ + (size_t)i * c.mp;
     const int step = (int)gridDim.y * kRowThreads;
     for (int k = (int)blockIdx.y * kRowThreads + tid; k < c.m; k += step)
-        unsafeAtomicAdd(&s_D[sr[k]], (double)c.dep[k]);
+        atomicAdd(&s_A[sr[k]], fixed_of(c.dep[k], e_min));
     __syncthreads();
     for (int j = tid; j < c.n; j += kRowThreads) {
-        const double v = s_D[j];
-        if (v != 0.0) {
+        const unsigned long long a = s_A[j];
+        if (a != 0ull) {
             const int lo = i < j ? i : j, hi = i < j ? j : i;
-            unsafeAtomicAdd(&c.delta[(size_t)lo * c.ld + hi], v);
+            unsafeAtomicAdd(&c.delta[(size_t)lo * c.ld + hi], value_of(a, e_min));
         }
     }
 }
@@ -362,7 +390,7 @@ dim3 cell_grid(const Colony& c) { return dim3((c.ld / 4 + 255) / 256, c.n); }
 
 hipError_t launch_update_gather(const Colony& c, hipStream_t s) {
     hipLaunchKernelGGL(k_update_gather, dim3(c.n), dim3(kGatherThreads),
-                       (size_t)c.ld * sizeof(double), s, c);
+                       (size_t)c.ld * sizeof(unsigned long long), s, c);
     return hipGetLastError();
 }
 
@@ -370,7 +398,7 @@ hipError_t launch_update_atomic(const Colony& c, bool combine_in_lds, hipStream_
     if (!c.delta) return hipErrorInvalidValue;
     if (combine_in_lds)
         hipLaunchKernelGGL(k_deposit_shared, dim3(c.n, deposit_slices(c.n, c.m)),
-                           dim3(kRowThreads), (size_t)c.ld * sizeof(double), s, c);
+                           dim3(kRowThreads), (size_t)c.ld * sizeof(unsigned long long), s, c);
     else
         hipLaunchKernelGGL(k_deposit_atomic, dim3((c.n + 255) / 256, c.m), dim3(256), 0, s, c);
     const int nt = c.ld / kTile;
@@ -400,7 +428,7 @@ hipError_t launch_update_gather_batch(const Colony* cols, const uint32_t* rowmap
                                       int max_ld, hipStream_t s) {
     if (total_rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_update_gather_batch, dim3(total_rows), dim3(kRowThreads),
-                       (size_t)max_ld * sizeof(double), s, cols, rowmap);
+                       (size_t)max_ld * sizeof(unsigned long long), s, cols, rowmap);
     return hipGetLastError();
 }
 
