@@ -307,6 +307,23 @@ def test_max_cities_sampled(rule):
     c.close()
 
 
+def test_deposit_sums_at_the_exactness_bound():
+    """The widest spread of tour lengths the library accepts at m = 65535:
+    a ring of unit edges with chords of 3000 (every tour between 20 and
+    60000, so 16 + 13 + 24 = 53 bits), where the deposit sums of a cell use
+    nearly all 53 bits.  Every tour, length and tau bit-exact over 2
+    iterations, all three updates (the gather and shared-memory ones sum in
+    fixed point, the direct one in binary64)."""
+    n = 20
+    d = np.full((n, n), 3000, np.int32)
+    for i in range(n):
+        d[i, (i + 1) % n] = d[(i + 1) % n, i] = 1
+    np.fill_diagonal(d, 0)
+    ref = compare_run(d, 65535, 1, 2, 0.5, 11, iters=2,
+                      kinds=("gather", "atomic", "atomic_direct"))
+    assert ref.best_len >= n
+
+
 def test_max_ants():
     """m = 65535 ants, the largest colony (one workgroup per ant, the top of
     the 16-bit ant field): every tour, length and tau bit-exact, all three
