@@ -83,20 +83,10 @@ __device__ __forceinline__ float s64_scan(float x) {
     return x;
 }
 
-// Stage A of S64 alone: the inclusive prefix of lanes 0..15 (row 0), which
-// stage B leaves as it is.  Equal to s64_scan on lanes 0..15; the other rows
-// hold their own row prefixes.
-__device__ __forceinline__ float s64_scan_row0(float x) {
-    x = x + dpp_move<0x111, 0xF>(x);
-    x = x + dpp_move<0x112, 0xF>(x);
-    x = x + dpp_move<0x114, 0xF>(x);
-    x = x + dpp_move<0x118, 0xF>(x);
-    return x;
-}
-
 // The first L levels of stage A (L = 1..4).  On lanes 0 .. 2^L - 1 of
-// non-negative values this equals s64_scan_row0: the later levels would add
-// +0 there (their source lane is below 0), which changes no value >= +0.
+// non-negative values this equals s64_scan (stage B leaves row 0 as it is,
+// and the later levels of stage A would add +0 there, their source lane
+// being below 0, which changes no value >= +0).
 template <int L>
 __device__ __forceinline__ float s64_scan_row0_levels(float x) {
     static_assert(L >= 1 && L <= 4, "one to four levels");
@@ -109,15 +99,6 @@ __device__ __forceinline__ float s64_scan_row0_levels(float x) {
 
 // Lane l receives lane l-1's value, lane 0 receives +0.
 __device__ __forceinline__ float wave_shift_up1(float x) { return dpp_move<0x138, 0xF>(x); }
-
-// Balanced pairwise sum over groups of 8 consecutive lanes: lane 8r+7 ends
-// with ((l0+l1)+(l2+l3)) + ((l4+l5)+(l6+l7)) of its group.
-__device__ __forceinline__ float octet_pairwise(float x) {
-    x = x + dpp_move<0x111, 0xF>(x);
-    x = x + dpp_move<0x112, 0xF>(x);
-    x = x + dpp_move<0x114, 0xF>(x);
-    return x;
-}
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 

@@ -20,7 +20,6 @@ struct Tile {
     static_assert(G == 4 || G == 8, "tile must be 4 or 8 cities per lane");
     static constexpr int kPass = 64 * G;          // cities per pass
     static constexpr int kLanesPerBlock = 64 / G; // lanes holding one 64-city block
-    static constexpr int kMaxPasses = 64 / G;     // lane bit set holds 64 bits
 };
 
 // Visited bits of block b, kept in lane b of a register pair: bit t set <=>
