@@ -293,30 +293,35 @@ def random_rows_rate(torch, aco, n: int, m: int, rows: int) -> float:
     return round(4.0 * n * m * (n - 1) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
 
 
-def random_rows_ceiling(torch, aco, n: int, m: int, waves_factors=(1, 4, 8)) -> dict:
+def random_rows_ceiling(torch, aco, n: int, m: int, waves_factors=(1, 2, 4, 8),
+                        in_flight=(1, 2)) -> dict:
     """Best rate of reading random whole rows of an n x ld matrix (the choice
-    matrix's footprint) with m, 4m and 8m one-wave workgroups: the memory
-    system's limit for this access pattern, where each XCD's L2 keeps a share
-    of the rows (a sequential sweep of the footprint keeps none), measured
-    with up to eight times the wavefronts construction has in flight."""
+    matrix's footprint) with 1, 2, 4 and 8 times m one-wave workgroups, each
+    keeping one or two rows in flight: the memory system's limit for this
+    access pattern, where each XCD's L2 keeps a share of the rows (a
+    sequential sweep of the footprint keeps none), measured with up to
+    sixteen times the rows construction has in flight."""
     stream = torch.cuda.current_stream()
     ld = (n + 63) // 64 * 64
     sink = torch.zeros(max(8 * m, 4096), dtype=torch.float32, device="cuda")
     mat = torch.rand(n * ld, dtype=torch.float32, device="cuda")
     by = {}
     for f in waves_factors:
-        waves = f * m
-        steps = max(16, m * (n - 1) // (2 * waves))
-        aco.probe_rows(mat, n, ld, n, waves, 4, sink)
-        e0, e1 = _events(torch)
-        e0.record(stream)
-        aco.probe_rows(mat, n, ld, n, waves, steps, sink)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        by[waves] = round(4.0 * n * waves * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        for r in in_flight:
+            waves = f * m
+            steps = max(16, m * (n - 1) // (2 * waves))
+            steps += (-steps) % r
+            aco.probe_rows(mat, n, ld, n, waves, 4, sink, rows_in_flight=r)
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            aco.probe_rows(mat, n, ld, n, waves, steps, sink, rows_in_flight=r)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            by[f"{waves}x{r}"] = round(4.0 * n * waves * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9,
+                                       1)
     del mat
     best = max(by, key=by.get)
-    return {"GBps": by[best], "waves": best, "by_waves_GBps": by}
+    return {"GBps": by[best], "shape": best, "by_shape_GBps": by}
 
 
 def requested_bytes(tours: np.ndarray, n: int, skip: bool) -> int:
@@ -791,14 +796,15 @@ def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool)
                               f"{ceil['loads_in_flight']} loads in flight"
                               f"{', nontemporal' if ceil['nontemporal'] else ''}, "
                               f"{ceil['reps']} passes, {ceil['ms']} ms), and random whole rows "
-                              f"with 1, 4 and 8 times the kernel's {m} wavefronts "
-                              f"(aco_probe_rows: {rows_ceil['GBps']} GB/s with "
-                              f"{rows_ceil['waves']}), where each XCD's L2 keeps a share of the "
+                              f"with 1, 2, 4 and 8 times the kernel's {m} wavefronts and one or "
+                              f"two rows in flight each (aco_probe_rows_shape: "
+                              f"{rows_ceil['GBps']} GB/s with wavefronts x rows in flight = "
+                              f"{rows_ceil['shape']}), where each XCD's L2 keeps a share of the "
                               f"rows as it does for the kernel"),
                 "peak_stream_GBps": ceil["GBps"],
                 "peak_by_shape_GBps": ceil["by_shape_GBps"],
                 "peak_random_rows_GBps": rows_ceil["GBps"],
-                "peak_random_rows_by_waves_GBps": rows_ceil["by_waves_GBps"],
+                "peak_random_rows_by_shape_GBps": rows_ceil["by_shape_GBps"],
                 "hbm_peak": HBM_PEAK_GBPS, "frac_of_hbm_peak": round(achieved / HBM_PEAK_GBPS, 4),
                 "requested_bytes_per_launch": req,
                 "requested_GBps": round(req / (con_ms * 1e-3) / 1e9, 1),

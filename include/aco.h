@@ -515,6 +515,11 @@ aco_status aco_probe_philox(int32_t waves, int32_t steps, uint32_t seed, uint32_
  * Asynchronous. */
 aco_status aco_probe_rows(const float* mat_dev, int32_t rows, int32_t ld, int32_t row_len,
                           int32_t waves, int32_t steps, float* sink_dev, void* hip_stream);
+/* As aco_probe_rows with `rows_in_flight` (1 or 2) steps' rows loaded by a
+ * wavefront before any of them is used.  Asynchronous. */
+aco_status aco_probe_rows_shape(const float* mat_dev, int32_t rows, int32_t ld,
+                                int32_t row_len, int32_t waves, int32_t steps,
+                                int32_t rows_in_flight, float* sink_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -112,6 +112,7 @@ def _load():
         "aco_probe_read": (i32, [vp, sz, i32, vp, vp]),
         "aco_probe_read_shape": (i32, [vp, sz, i32, i32, i32, vp, vp]),
         "aco_probe_rows": (i32, [vp, i32, i32, i32, i32, i32, vp, vp]),
+        "aco_probe_rows_shape": (i32, [vp, i32, i32, i32, i32, i32, i32, vp, vp]),
         "aco_probe_philox": (i32, [i32, i32, u32, vp, vp]),
     }
     for name, (res, args) in sigs.items():
@@ -496,10 +497,10 @@ def probe_copy(dst, src, stream=None):
 
 
 def probe_rows(mat, rows: int, ld: int, row_len: int, waves: int, steps: int, sink,
-               stream=None):
-    _check(lib.aco_probe_rows(ctypes.c_void_p(mat.data_ptr()), rows, ld, row_len, waves, steps,
-                              ctypes.c_void_p(sink.data_ptr()), _stream_handle(stream)),
-           "aco_probe_rows")
+               stream=None, rows_in_flight: int = 1):
+    _check(lib.aco_probe_rows_shape(ctypes.c_void_p(mat.data_ptr()), rows, ld, row_len, waves,
+                                    steps, rows_in_flight, ctypes.c_void_p(sink.data_ptr()),
+                                    _stream_handle(stream)), "aco_probe_rows_shape")
 
 
 def probe_philox(waves: int, steps: int, seed: int, sink, stream=None):

@@ -696,17 +696,27 @@ aco_status aco_probe_philox(int32_t waves, int32_t steps, uint32_t seed, uint32_
     return ACO_OK;
 }
 
-aco_status aco_probe_rows(const float* mat_dev, int32_t rows, int32_t ld, int32_t row_len,
-                          int32_t waves, int32_t steps, float* sink_dev, void* hip_stream) {
+aco_status aco_probe_rows_shape(const float* mat_dev, int32_t rows, int32_t ld,
+                                int32_t row_len, int32_t waves, int32_t steps,
+                                int32_t rows_in_flight, float* sink_dev, void* hip_stream) {
     if (rows < 1 || row_len < 1 || row_len > aco::kMaxCities || ld < row_len || (ld % 4) != 0)
         return fail(ACO_ERR_INVALID, "need rows >= 1, 1 <= row_len <= 4096, ld >= row_len, ld % 4 == 0");
     if (waves < 0 || steps < 0) return fail(ACO_ERR_INVALID, "waves and steps must be >= 0");
+    if (rows_in_flight != 1 && rows_in_flight != 2)
+        return fail(ACO_ERR_INVALID, "rows_in_flight must be 1 or 2");
     if (waves > 0 && (!mat_dev || !sink_dev)) return fail(ACO_ERR_INVALID, "NULL device pointer");
     if (((uintptr_t)mat_dev % 16) != 0) return fail(ACO_ERR_INVALID, "matrix must be 16-byte aligned");
-    const hipError_t e = aco::launch_probe_rows(mat_dev, rows, ld, row_len, waves, steps, sink_dev,
-                                                static_cast<hipStream_t>(hip_stream));
+    const hipError_t e =
+        aco::launch_probe_rows(mat_dev, rows, ld, row_len, waves, steps, rows_in_flight, sink_dev,
+                               static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return device_fail(nullptr, e, "aco_probe_rows");
     return ACO_OK;
+}
+
+aco_status aco_probe_rows(const float* mat_dev, int32_t rows, int32_t ld, int32_t row_len,
+                          int32_t waves, int32_t steps, float* sink_dev, void* hip_stream) {
+    return aco_probe_rows_shape(mat_dev, rows, ld, row_len, waves, steps, 1, sink_dev,
+                                hip_stream);
 }
 
 }  // extern "C"

@@ -83,7 +83,7 @@ hipError_t launch_test_select(int tile, int n, int count, const float* rows,
                               hipStream_t s);
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
-                             int steps, float* sink, hipStream_t s);
+                             int steps, int rows_in_flight, float* sink, hipStream_t s);
 // loads: 16-byte loads in flight per thread (4, 8 or 16); nontemporal loads
 // keep nothing in the caches.
 hipError_t launch_probe_read(const void* src, size_t bytes, int reps, int loads, bool nontemporal,

@@ -78,49 +78,66 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 
 typedef unsigned int probe_u32x4 __attribute__((ext_vector_type(4)));
 
-template <int P>
+// R rows in flight per wavefront: the loads of R consecutive steps' rows are
+// issued before any of them is used.
+template <int P, int R>
 __global__ __launch_bounds__(64) void k_probe_rows(const float* mat, int rows, int ld,
                                                    int row_len, int steps, float* sink) {
     const int lane = threadIdx.x;
     uint32_t acc = 0;
-    for (int s = 0; s < steps; ++s) {
-        const uint32_t h = mix32((uint32_t)blockIdx.x * 0x9E3779B9u + (uint32_t)s);
-        const int r = (int)(((uint64_t)h * (uint32_t)rows) >> 32);
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float*>(mat + (size_t)r * ld), (short)0, ((row_len + 3) & ~3) * 4,
-            0x00020000);
-        probe_u32x4 a[P], b[P];
+    for (int s0 = 0; s0 < steps; s0 += R) {
+        probe_u32x4 a[R][P], b[R][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            const int off = (p * 512 + lane * 8) * 4;
-            a[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
-            b[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+        for (int q = 0; q < R; ++q) {
+            const int s = s0 + q < steps ? s0 + q : steps - 1;
+            const uint32_t h = mix32((uint32_t)blockIdx.x * 0x9E3779B9u + (uint32_t)s);
+            const int r = (int)(((uint64_t)h * (uint32_t)rows) >> 32);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(mat + (size_t)r * ld), (short)0, ((row_len + 3) & ~3) * 4,
+                0x00020000);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int off = (p * 512 + lane * 8) * 4;
+                a[q][p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+                b[q][p] = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0);
+            }
         }
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-            acc ^= a[p].x ^ a[p].y ^ a[p].z ^ a[p].w ^ b[p].x ^ b[p].y ^ b[p].z ^ b[p].w;
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                acc ^= a[q][p].x ^ a[q][p].y ^ a[q][p].z ^ a[q][p].w ^ b[q][p].x ^ b[q][p].y ^
+                       b[q][p].z ^ b[q][p].w;
     }
     if (acc == 0x12345678u) sink[blockIdx.x] = 1.0f;  // keeps the loads alive
+}
+
+template <int R>
+hipError_t launch_probe_rows_r(const float* mat, int rows, int ld, int row_len, int waves,
+                               int steps, float* sink, hipStream_t s) {
+    const dim3 g(waves), b(64);
+    switch ((row_len + 511) / 512) {
+        case 1: hipLaunchKernelGGL((k_probe_rows<1, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 2: hipLaunchKernelGGL((k_probe_rows<2, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 3: hipLaunchKernelGGL((k_probe_rows<3, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 4: hipLaunchKernelGGL((k_probe_rows<4, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 5: hipLaunchKernelGGL((k_probe_rows<5, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 6: hipLaunchKernelGGL((k_probe_rows<6, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 7: hipLaunchKernelGGL((k_probe_rows<7, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        case 8: hipLaunchKernelGGL((k_probe_rows<8, R>), g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_probe_rows(const float* mat, int rows, int ld, int row_len, int waves,
-                             int steps, float* sink, hipStream_t s) {
+                             int steps, int rows_in_flight, float* sink, hipStream_t s) {
     if (waves <= 0 || steps <= 0) return hipSuccess;
-    const dim3 g(waves), b(64);
-    switch ((row_len + 511) / 512) {
-        case 1: hipLaunchKernelGGL(k_probe_rows<1>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 2: hipLaunchKernelGGL(k_probe_rows<2>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 3: hipLaunchKernelGGL(k_probe_rows<3>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 4: hipLaunchKernelGGL(k_probe_rows<4>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 5: hipLaunchKernelGGL(k_probe_rows<5>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 6: hipLaunchKernelGGL(k_probe_rows<6>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 7: hipLaunchKernelGGL(k_probe_rows<7>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        case 8: hipLaunchKernelGGL(k_probe_rows<8>, g, b, 0, s, mat, rows, ld, row_len, steps, sink); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (rows_in_flight == 1) return launch_probe_rows_r<1>(mat, rows, ld, row_len, waves, steps, sink, s);
+    if (rows_in_flight == 2) return launch_probe_rows_r<2>(mat, rows, ld, row_len, waves, steps, sink, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
