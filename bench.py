@@ -55,8 +55,12 @@ WORKLOADS = {
 }
 ALPHA, BETA, RHO = 1, 2, 0.5
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "construct_n2400_traffic.json")
+# The text the construction kernel is compiled from: its source, the headers
+# of its device code, and (of the state header, which also declares host
+# launchers) the colony struct it takes as its argument.
 KERNEL_SOURCES = ["paper_1101_2678_amd/csrc/construct.hip", "paper_1101_2678_amd/csrc/r64_lanes.hpp",
-                  "paper_1101_2678_amd/csrc/aco_device.hpp", "paper_1101_2678_amd/csrc/aco_state.hpp"]
+                  "paper_1101_2678_amd/csrc/aco_device.hpp"]
+KERNEL_STRUCT = ("paper_1101_2678_amd/csrc/aco_state.hpp", "struct Colony {", "};")
 
 
 def log(msg):
@@ -68,6 +72,11 @@ def kernel_source_hash() -> str:
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
+    rel, start, end = KERNEL_STRUCT
+    with open(os.path.join(ROOT, rel)) as f:
+        text = f.read()
+    i = text.index(start)
+    h.update(text[i:text.index(end, i) + len(end)].encode())
     return h.hexdigest()
 
 
