@@ -303,9 +303,12 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
 // launch has n <= 512 P8), so a batch of small instances holds no registers
 // for rows it does not have; tile 4 is only ever set for n <= 1024 (4
 // passes).
-// Loads first in the batched launch too: 754 -> 761 solves/s on the
-// 256-instance workload (n 50..1000, same box).
-constexpr bool kBatchLoadFirst = true;
+// Loads first in the batched launch too, for rows of one or two passes (as
+// in the single-instance launch): 757 -> 764 solves/s on the 256-instance
+// workload (n 50..1000, same box).  Longer rows keep the bookkeeping first,
+// which is faster where construction is bound by memory.
+template <int NP>
+constexpr bool kBatchLoadFirst = NP < 3;
 
 // The ant's code for its colony's exact pass count NP (1 .. PMAX): each
 // instance runs a loop specialised for its row length, with no per-pass
@@ -320,7 +323,7 @@ __device__ __forceinline__ void batch_ant(const Colony& c, int k, uint32_t iter,
             return;
         }
     }
-    construct_ant<G, NP, true, kBatchLoadFirst>(c, k, iter, s_tour, sh);
+    construct_ant<G, NP, true, kBatchLoadFirst<NP>>(c, k, iter, s_tour, sh);
 }
 
 template <int P8>
