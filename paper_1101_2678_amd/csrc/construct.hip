@@ -229,9 +229,10 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
 
     // LOAD_FIRST: a step's row loads go out as soon as its city is known, and
     // the bookkeeping of that city (tour entry, visited bits) is done while
-    // they are in flight.  That shortens latency-bound launches (one or two
-    // passes: n = 1000 7%, n = 100 14% faster) but made the bandwidth-bound
-    // n = 2400 launch 1% slower, which keeps the bookkeeping first.  With
+    // they are in flight.  That shortens launches of one to three passes
+    // (n = 100 14%, n = 1000 7%, n = 1500 4% faster) but made the
+    // bandwidth-bound four- and five-pass launches (n = 2048, 2400) no
+    // faster or up to 1% slower, which keep the bookkeeping first.  With
     // LOAD_FIRST the loads see the visited bits without the step's own city;
     // with SKIP that only loads a quad once more, and masking (which sees
     // it) zeroes the city.
@@ -293,7 +294,7 @@ template <int G, int P>
 __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
     extern __shared__ uint16_t s_tour[];
     __shared__ __align__(16) AntShared sh;
-    construct_ant<G, P, (P >= 3), (P < 3)>(c, ant_of_block(blockIdx.x, c.m), iter, s_tour, sh);
+    construct_ant<G, P, (P >= 3), (P < 4)>(c, ant_of_block(blockIdx.x, c.m), iter, s_tour, sh);
 }
 
 // Batched construction: workgroup g builds ant (antmap[g] & 0xffff) of colony
@@ -303,12 +304,12 @@ __global__ __launch_bounds__(64) void k_construct(Colony c, uint32_t iter) {
 // launch has n <= 512 P8), so a batch of small instances holds no registers
 // for rows it does not have; tile 4 is only ever set for n <= 1024 (4
 // passes).
-// Loads first in the batched launch too, for rows of one or two passes (as
+// Loads first in the batched launch too, for rows of one to three passes (as
 // in the single-instance launch): 757 -> 764 solves/s on the 256-instance
 // workload (n 50..1000, same box).  Longer rows keep the bookkeeping first,
-// which is faster where construction is bound by memory.
+// which is no slower where construction is bound by memory.
 template <int NP>
-constexpr bool kBatchLoadFirst = NP < 3;
+constexpr bool kBatchLoadFirst = NP < 4;
 
 // The ant's code for its colony's exact pass count NP (1 .. PMAX): each
 // instance runs a loop specialised for its row length, with no per-pass
