@@ -30,6 +30,8 @@
 //     tree, in block order, until the first feasible prefix above the target.
 // Random numbers: Philox draws (seed, iter, ant, step), 64 steps at a time on
 // the vector unit.
+#include <type_traits>
+
 #include "r64_lanes.hpp"
 
 namespace aco {
@@ -50,15 +52,22 @@ __device__ __forceinline__ uint64_t initial_lane_bits(int n, int lane) {
     return bits;
 }
 
+// The per-lane feasibility bits in 32 bits where P G <= 32 (rows of up to
+// 1024 cities), so that clearing one takes 32-bit operations only.
+template <int G, int P>
+using LaneBits = std::conditional_t<(P * G <= 32), uint32_t, uint64_t>;
+
 // Marks city j visited in both tabu representations (called with j uniform).
-template <int G>
-__device__ __forceinline__ void mark_visited(int j, int lane, uint64_t& lane_bits,
+template <int G, typename B>
+__device__ __forceinline__ void mark_visited(int j, int lane, B& lane_bits,
                                              uint64_t& block_bits) {
-    if (lane == (j >> 6)) block_bits |= 1ull << (j & 63);
-    const int owner = (j % Tile<G>::kPass) / G;
-    const int bit = (j / Tile<G>::kPass) * G + (j % G);
+    // j >= 0: unsigned, so the divisions are shifts and masks
+    const uint32_t uj = (uint32_t)j;
+    if (lane == (int)(uj >> 6)) block_bits |= 1ull << (uj & 63);
+    const int owner = (int)((uj % Tile<G>::kPass) / G);
+    const int bit = (int)((uj / Tile<G>::kPass) * G + (uj % G));
     // a select rather than a branch around the owner lane
-    lane_bits &= lane == owner ? ~(1ull << bit) : ~0ull;
+    lane_bits &= lane == owner ? ~((B)1 << bit) : ~(B)0;
 }
 
 // Stages the masked weights of block `b` into s_w (city 64b + t at
@@ -96,12 +105,12 @@ __device__ __forceinline__ void stage_block(const u32x4 (&wa)[P], const u32x4 (&
 // cities but inside the span read padding or the next row, and masking
 // (whose bits exist only for cities < n) zeroes them.  With SKIP, a 16-byte
 // load whose four cities are all visited goes out of range instead.
-template <int G, int P, bool SKIP>
+template <int G, int P, bool SKIP, typename B>
 __device__ __forceinline__ void load_row(const float* __restrict__ mat, int records, int row,
-                                         int ld, uint64_t lane_bits, int lane, u32x4 (&wa)[P],
+                                         int row_bytes, B lane_bits, int lane, u32x4 (&wa)[P],
                                          u32x4 (&wb)[P]) {
     const __amdgpu_buffer_rsrc_t rs = row_rsrc(mat, records);
-    const int soff = row * ld * 4;
+    const int soff = row * row_bytes;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
@@ -128,13 +137,21 @@ constexpr bool kWriteAllPasses = (P * Tile<G>::kPass <= 1024);
 // Wave-uniform.  The workgroup is one wavefront: its LDS operations execute
 // in program order, and every LDS access below uses a lane-dependent index,
 // so the compiler keeps the order.
-template <int G, int P>
-__device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n,
-                                           uint64_t lane_bits, uint64_t block_bits, float* s_T,
-                                           float* s_w, float u, int lane) {
+template <int G, int P, typename B>
+__device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n, B lane_bits,
+                                           uint64_t block_bits, float* s_T, float* s_w, float u,
+                                           int lane) {
     constexpr int LPB = Tile<G>::kLanesPerBlock;
     constexpr bool kAll = kWriteAllPasses<G, P>;
+    // Block totals to lane b (0 past the row's blocks).  Rows of two to four
+    // passes staged whole fetch them with cross-lane reads from the last
+    // lane of each group and stage the weights afterwards (n = 1000: 4%
+    // faster than through an LDS store and load); rows of one pass keep the
+    // store and load (cross-lane reads measured 6% slower at n = 512), and
+    // so do longer rows.
+    constexpr bool kPermute = kAll && P >= 2;
     const int nb = (n + 63) >> 6;
+    float T = 0.0f;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const uint32_t bits = (uint32_t)(lane_bits >> (p * G));
@@ -146,18 +163,34 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
         } else {
             t = pair_sum4(wa[p]);
         }
-        if (kAll) {
+        if (kAll && !kPermute) {
             u32x4* dst = reinterpret_cast<u32x4*>(s_w + p * Tile<G>::kPass + lane * G);
             dst[0] = wa[p];
             if (G == 8) dst[1] = wb[p];
         }
         t = group_pairwise<LPB>(t);
-        if ((lane % LPB) == LPB - 1) s_T[p * G + lane / LPB] = t;
+        if (kPermute) {
+            // block b = pass p, group b mod G
+            const float x = __int_as_float(__builtin_amdgcn_ds_bpermute(
+                ((lane % G) * LPB + LPB - 1) * 4, __float_as_int(t)));
+            T = lane / G == p ? x : T;
+        } else if ((lane % LPB) == LPB - 1) {
+            s_T[p * G + lane / LPB] = t;
+        }
+    }
+    if (kPermute) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            u32x4* dst = reinterpret_cast<u32x4*>(s_w + p * Tile<G>::kPass + lane * G);
+            dst[0] = wa[p];
+            if (G == 8) dst[1] = wb[p];
+        }
+    } else {
+        T = s_T[lane];
     }
     // Rows of at most 1024 cities have nb <= 16 blocks, all in row 0 of the
     // block-total scan, which stage B leaves as it is; rows of at most 2^L
     // blocks need only its first L levels.
-    const float T = s_T[lane];
     float I;
     if constexpr (kAll)
         I = s64_scan_row0_levels<block_scan_levels(P * G)>(T);
@@ -170,9 +203,12 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
     uint64_t cand = ballot(bound > target) & (nb >= 64 ? ~0ull : (1ull << nb) - 1ull);
     // Nearly always exactly one candidate block: a single-exit loop, tested
     // at the bottom, so that the usual step runs through without a taken
-    // branch.
+    // branch.  It goes on while `more` (the remaining candidates, or 0 once
+    // the city is found) is not 0, made opaque so that the test stays one
+    // compare of a register pair.
     int j = -1;
     if (__builtin_expect(cand != 0, 1)) {
+        uint64_t more;
         do {
             const int b = __builtin_ctzll(cand);
             cand &= cand - 1;
@@ -188,18 +224,20 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
             const float eb = read_lane(E, b);
             const uint64_t hit = ballot((eb + s) > target) & ~vis;
             if (hit) j = b * 64 + __builtin_ctzll(hit);
-        } while (__builtin_expect(j < 0 && cand != 0, 0));
+            more = hit != 0 ? 0ull : cand;
+            __asm__("" : "+s"(more));
+        } while (__builtin_expect(more != 0, 0));
     }
     if (__builtin_expect(j >= 0, 1)) return j;
     return pick_fallback(block_bits);
 }
 
-template <int G, int P, bool SKIP>
+template <int G, int P, bool SKIP, typename B>
 __device__ __forceinline__ int r64_pick(const float* __restrict__ mat, int records, int row,
-                                        int ld, int n, uint64_t lane_bits, uint64_t block_bits,
+                                        int row_bytes, int n, B lane_bits, uint64_t block_bits,
                                         float* s_T, float* s_w, float u, int lane) {
     u32x4 wa[P], wb[P];
-    load_row<G, P, SKIP>(mat, records, row, ld, lane_bits, lane, wa, wb);
+    load_row<G, P, SKIP>(mat, records, row, row_bytes, lane_bits, lane, wa, wb);
     return pick_loaded<G, P>(wa, wb, n, lane_bits, block_bits, s_T, s_w, u, lane);
 }
 
@@ -219,9 +257,10 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     const int records = n * c.ld * 4;  // the whole n x ld choice matrix
     const PhiloxKey key{(uint32_t)c.seed, (uint32_t)(c.seed >> 32)};
 
+    const int row_bytes = c.ld * 4;
     uint64_t block_bits = initial_block_bits(n, lane);
     sh.T[lane] = 0.0f;
-    uint64_t lane_bits = initial_lane_bits<G, P>(n, lane);
+    LaneBits<G, P> lane_bits = (LaneBits<G, P>)initial_lane_bits<G, P>(n, lane);
     __syncthreads();
 
     const uint32_t x0 = draw(key, iter, (uint32_t)k, 0u);
@@ -240,7 +279,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
     if (LOAD_FIRST) {
         for (int step = 1; step < n; ++step) {
             u32x4 wa[P], wb[P];
-            load_row<G, P, SKIP>(c.choice, records, cur, c.ld, lane_bits, lane, wa, wb);
+            load_row<G, P, SKIP>(c.choice, records, cur, row_bytes, lane_bits, lane, wa, wb);
             if (lane == 0) s_tour[step - 1] = (uint16_t)cur;
             mark_visited<G>(cur, lane, lane_bits, block_bits);
             const int slot = (step - 1) & 63;
@@ -262,7 +301,7 @@ __device__ __forceinline__ void construct_ant(const Colony& c, int k, uint32_t i
             if (__builtin_expect(slot == 0, 0))
                 u64 = draws64(key, iter, (uint32_t)k, step, lane);
             const float u = read_lane(u64, slot);
-            const int j = r64_pick<G, P, SKIP>(c.choice, records, cur, c.ld, n, lane_bits,
+            const int j = r64_pick<G, P, SKIP>(c.choice, records, cur, row_bytes, n, lane_bits,
                                                block_bits, sh.T, sh.w, u, lane);
             cur = j < 0 ? 0 : j;
         }
@@ -374,7 +413,7 @@ __global__ __launch_bounds__(64) void k_test_select(const float* rows, int ld, i
     __syncthreads();
     // one row per query: the span is that row's n cities (rounded up to whole
     // 16-byte loads; the caller's padding columns are zero)
-    const int j = r64_pick<G, P, true>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld, n,
+    const int j = r64_pick<G, P, true>(rows + (size_t)q * ld, ((n + 3) & ~3) * 4, 0, ld * 4, n,
                                        lane_bits, vis, sh.T, sh.w, us[q], lane);
     if (lane == 0) out[q] = j;
 }

@@ -268,10 +268,12 @@ __device__ __forceinline__ uint64_t initial_bits(int n, int w, int lane) {
 // Clears city j's bit in the lane (of the wave) that holds it.
 template <int W>
 __device__ __forceinline__ void mark_visited(int j, int w, int lane, uint64_t& bits) {
-    constexpr int GW = Lay<W>::GW;
-    const int p = j / kPass, rem = j - p * kPass;
-    const int jw = rem / (64 * GW), r2 = rem - jw * 64 * GW;
-    if (jw == w && r2 / GW == lane) bits &= ~(1ull << (GW * p + r2 % GW));
+    constexpr uint32_t GW = Lay<W>::GW;
+    // j >= 0: unsigned, so the divisions are shifts and masks
+    const uint32_t uj = (uint32_t)j;
+    const uint32_t p = uj / kPass, rem = uj - p * kPass;
+    const uint32_t jw = rem / (64 * GW), r2 = rem - jw * 64 * GW;
+    if ((int)jw == w && (int)(r2 / GW) == lane) bits &= ~(1ull << (GW * p + r2 % GW));
 }
 
 // Wavefronts per ant of the construction kernel (and of its verification

@@ -43,11 +43,13 @@ __device__ __forceinline__ uint64_t initial_lane_bits_split(int n, int wv, int l
 template <int G, int W>
 __device__ __forceinline__ void mark_visited_split(int j, int wv, int lane, uint64_t& lane_bits,
                                                    uint64_t& block_bits) {
-    if (lane == (j >> 6)) block_bits |= 1ull << (j & 63);
-    const int p = j / Tile<G>::kPass;
-    const int owner = (j % Tile<G>::kPass) / G;
-    const int bit = (p / W) * G + (j % G);
-    lane_bits &= (p % W == wv && lane == owner) ? ~(1ull << bit) : ~0ull;
+    // j >= 0: unsigned, so the divisions are shifts and masks
+    const uint32_t uj = (uint32_t)j;
+    if (lane == (int)(uj >> 6)) block_bits |= 1ull << (uj & 63);
+    const uint32_t p = uj / Tile<G>::kPass;
+    const int owner = (int)((uj % Tile<G>::kPass) / G);
+    const int bit = (int)((p / W) * G + (uj % G));
+    lane_bits &= ((int)(p % W) == wv && lane == owner) ? ~(1ull << bit) : ~0ull;
 }
 
 // One R64 draw by the W waves of the workgroup over a row loaded with
