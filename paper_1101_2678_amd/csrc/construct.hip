@@ -143,13 +143,13 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
                                            int lane) {
     constexpr int LPB = Tile<G>::kLanesPerBlock;
     constexpr bool kAll = kWriteAllPasses<G, P>;
-    // Block totals to lane b (0 past the row's blocks).  Rows of two to four
-    // passes staged whole fetch them with cross-lane reads from the last
-    // lane of each group and stage the weights afterwards (n = 1000: 4%
-    // faster than through an LDS store and load); rows of one pass keep the
-    // store and load (cross-lane reads measured 6% slower at n = 512), and
-    // so do longer rows.
-    constexpr bool kPermute = kAll && P >= 2;
+    // Block totals to lane b (0 past the row's blocks).  Rows of two or more
+    // passes fetch them with one cross-lane read per pass from the last lane
+    // of each group (and rows staged whole store their weights afterwards):
+    // against a masked LDS store per pass and a load, n = 1000 4%, n = 1500
+    // 4.5%, n = 2400 0.8% faster.  Rows of one pass keep the store and load
+    // (cross-lane reads measured 6% slower at n = 512).
+    constexpr bool kPermute = P >= 2;
     const int nb = (n + 63) >> 6;
     float T = 0.0f;
 #pragma unroll
@@ -179,11 +179,13 @@ __device__ __forceinline__ int pick_loaded(u32x4 (&wa)[P], u32x4 (&wb)[P], int n
         }
     }
     if (kPermute) {
+        if (kAll) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            u32x4* dst = reinterpret_cast<u32x4*>(s_w + p * Tile<G>::kPass + lane * G);
-            dst[0] = wa[p];
-            if (G == 8) dst[1] = wb[p];
+            for (int p = 0; p < P; ++p) {
+                u32x4* dst = reinterpret_cast<u32x4*>(s_w + p * Tile<G>::kPass + lane * G);
+                dst[0] = wa[p];
+                if (G == 8) dst[1] = wb[p];
+            }
         }
     } else {
         T = s_T[lane];
