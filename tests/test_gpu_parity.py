@@ -126,6 +126,16 @@ def test_parity_three_and_four_passes(n):
     compare_run(d, 40, 1, 2, 0.5, seed=n + 3, iters=3)
 
 
+@pytest.mark.parametrize("n", [2049, 2113, 3000])
+def test_parity_five_and_six_passes(n):
+    """Rows of five and six 512-city passes around the first ragged sizes
+    past 2048 (ld = 2112, 2112, 3008) and with more LDS accumulators per
+    gather workgroup than at n = 2400: every tour, length, tau and choice
+    bit-exact over 3 iterations, gather and atomic."""
+    _, d = tsp_inputs.instance(n, "uniform", side=1_000_000, seed=n)
+    compare_run(d, 40, 1, 2, 0.5, seed=n + 5, iters=3)
+
+
 @pytest.mark.parametrize("layout", ["uniform", "cluster"])
 def test_parity_n1000_full(layout):
     """The n = m = 1000 workload in full (both layouts, instance seed 1,
