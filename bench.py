@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -67,16 +68,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def code_text(text: str) -> str:
+    """Source text without its comments, whitespace runs collapsed: what
+    the compiler sees, so that editing a comment does not mark the kernel as
+    changed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update(code_text(f.read()).encode())
     rel, start, end = KERNEL_STRUCT
     with open(os.path.join(ROOT, rel)) as f:
         text = f.read()
     i = text.index(start)
-    h.update(text[i:text.index(end, i) + len(end)].encode())
+    h.update(code_text(text[i:text.index(end, i) + len(end)]).encode())
     return h.hexdigest()
 
 

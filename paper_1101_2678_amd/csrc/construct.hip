@@ -20,8 +20,9 @@
 //     levels inside the lane, log2(64/G) DPP levels across the lanes.  That
 //     is exactly the last entry of the 64-wide S64 prefix tree, so every T_b
 //     is bit-identical to the roulette's definition whatever G is;
-//   * T_b move to lane b through LDS and are scanned with S64 (DPP), giving
-//     the block offsets E_b and the total;
+//   * T_b move to lane b (a cross-lane read per pass, or for rows of one
+//     pass an LDS store and load) and are scanned with S64 (DPP), giving the
+//     block offsets E_b and the total;
 //   * a block can hold the chosen city only if fl(E_b + T_b (1 + 2^-20)) >
 //     target: every inner prefix of a block is at most T_b (1 + 13 u) for a
 //     depth-6 tree of non-negative terms (u = 2^-24), so blocks failing this
