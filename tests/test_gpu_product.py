@@ -29,7 +29,7 @@ def _cuda():
 def _product_rows(n, count, rng):
     rows, feas, _ = _adversarial_rows(n, count, rng)
     u = (rng.integers(0, 2**24, size=(count, n)) / 2**24).astype(np.float32)
-    kind = rng.integers(0, 6, size=count)
+    kind = rng.integers(0, 9, size=count)
     for q in range(count):
         if kind[q] == 0:  # many equal products across lanes: weights 1, draws from a tiny set
             rows[q] = 1.0
@@ -45,6 +45,21 @@ def _product_rows(n, count, rng):
         elif kind[q] == 4:  # products near the binary32 tie boundary
             rows[q] = np.float32(1.0 + 2.0**-23)
             u[q] = rng.choice(np.array([1 - 2.0**-23, 1 - 2.0**-24], np.float32), size=n)
+        elif kind[q] == 5:  # the largest choice value draws low; smaller ones tie with it
+            rows[q] = 0.25
+            u[q] = 0.5
+            j = rng.integers(0, n)
+            rows[q, j], u[q, j] = 1.0, 0.125
+        elif kind[q] == 6:  # the largest choice value draws 0; the winner is far below it
+            rows[q] = np.float32(0.01)
+            j = rng.integers(0, n)
+            rows[q, j], u[q, j] = 1.0, 0.0
+        elif kind[q] == 7:  # choice values on and around half and an eighth of the largest
+            rows[q] = rng.choice(np.array([0.5, 0.125, np.float32(0.5 - 2.0**-25),
+                                           np.float32(0.125 - 2.0**-27)], np.float32), size=n)
+            u[q] = rng.choice(np.array([0.25, 0.5, 1 - 2.0**-24], np.float32), size=n)
+            j = rng.integers(0, n)
+            rows[q, j], u[q, j] = 1.0, 0.0625
     none = rng.random(count) < 0.02
     feas[none] = 0  # no feasible city: -1
     return rows, feas, u
