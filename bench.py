@@ -726,6 +726,39 @@ def bench_served(args, torch, aco):
     return rec
 
 
+ISOLATED_ANTS = 256  # one wavefront per compute unit, one per SIMD
+
+
+def latency_floor(torch, aco, d, n: int, m_iso: int, con_ms: float) -> dict:
+    """The construction step's latency with nothing to overlap it: the same
+    instance with m_iso ants (at most one wavefront per compute unit), mean
+    of 5 constructions after 2 iterations.  frac = that per-step time over
+    the workload's own, i.e. how close the workload comes to the chain of
+    dependent operations one step is."""
+    col = aco.Colony(d, m_iso, ALPHA, BETA, RHO, seed=1)
+    stream = torch.cuda.current_stream()
+    for it in range(2):
+        col.construct(it)
+        col.update("gather")
+    e0, e1 = _events(torch)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for it in range(2, 7):
+        col.construct(it)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    col.close()
+    iso_ns = e0.elapsed_time(e1) / 5 * 1e6 / (n - 1)
+    act_ns = con_ms * 1e6 / (n - 1)
+    return {"ns_per_step_isolated": round(iso_ns, 1), "ants_isolated": m_iso,
+            "ns_per_step": round(act_ns, 1), "frac": round(iso_ns / act_ns, 4),
+            "note": (f"one construction step is a chain of dependent operations (row load, "
+                     f"block sums, scans, pick); with {m_iso} ants no two wavefronts share a "
+                     f"SIMD, so their per-step time is the chain's own latency, the bound "
+                     f"of this latency-bound size; frac = that over this workload's "
+                     f"per-step time")}
+
+
 def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool) -> dict:
     """One resident instance of WORKLOADS[name]: `warmup` untimed iterations,
     then `steps` timed iterations (construction, then the update of
@@ -868,6 +901,10 @@ def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool)
         "best_len_after_run": int(best_len),
         "roofline": roofline,
     }
+    if roofline["bound"] == "l2" and m > ISOLATED_ANTS:
+        # latency-bound sizes (the matrix within one XCD's L2): the step chain's
+        # own latency, measured with few enough ants that no two share a SIMD
+        rec["latency_floor"] = latency_floor(torch, aco, d, n, ISOLATED_ANTS, con_ms)
     if main:
         # each update kernel against a copy of its own footprint (one launch)
         for kind in upd:
