@@ -861,6 +861,13 @@ def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool)
                 "requested_bytes_per_launch": req,
                 "requested_GBps": round(req / (con_ms * 1e-3) / 1e9, 1),
                 "frac_requested": round(req / (con_ms * 1e-3) / 1e9 / peak, 4)}
+    if passes >= 3:
+        roofline["frac_note"] = (
+            f"achieved counts the whole {n}-city row per ant-step (4n bytes), but the kernel "
+            f"does not load a 16-byte group of cities once all four are visited, so it requests "
+            f"only {req / alg:.3f} of those bytes: frac can reach 1 while the bytes it moves "
+            f"(frac_requested, and the counter bytes past L2 in frac_traffic_of_stream) stay "
+            f"below the measured ceiling")
     if main:
         traffic, traffic_note = traffic_from_profile()
         roofline["traffic"] = traffic
@@ -901,7 +908,7 @@ def run_single(args, torch, aco, name: str, steps: int, warmup: int, main: bool)
         "best_len_after_run": int(best_len),
         "roofline": roofline,
     }
-    if roofline["bound"] == "l2" and m > ISOLATED_ANTS:
+    if roofline["bound"] == "l2" and m > ISOLATED_ANTS and not args.no_latency_floor:
         # latency-bound sizes (the matrix within one XCD's L2): the step chain's
         # own latency, measured with few enough ants that no two share a SIMD
         rec["latency_floor"] = latency_floor(torch, aco, d, n, ISOLATED_ANTS, con_ms)
@@ -943,6 +950,10 @@ def main():
                          "ms_per_step then includes the round trips)")
     ap.add_argument("--no-product", action="store_true",
                     help="skip the product-and-argmax construction block")
+    ap.add_argument("--no-latency-floor", action="store_true",
+                    help="skip the isolated-chain timing of the L2-resident workloads (for "
+                         "profiled runs, whose per-kernel statistics would otherwise mix in "
+                         "its smaller launches)")
     ap.add_argument("--nn", type=int, default=30,
                     help="also time candidate-list construction with lists of this length "
                          "(0 skips it)")
