@@ -76,3 +76,14 @@ def test_requested_bytes_hand_count(bench):
     # n = 6 (groups {0..3}, {4, 5}): tour 5 0 4 1 2 3 -> last positions 5 and 2
     t = np.array([[5, 0, 4, 1, 2, 3, 5]], np.uint16)
     assert bench.requested_bytes(t, 6, skip=True) == 16 * (5 + 2)
+
+
+def test_kernel_hash_ignores_comments_only(bench):
+    """The traffic record's hash changes with the kernel's code, not with a
+    comment or the layout of its text."""
+    a = "int f(int x) {  // doubles\n    return 2 * x; /* twice */ }\n"
+    b = "int f(int x) {\n  return 2 * x;\n}  // twice x\n"
+    c = "int f(int x) { return 3 * x; }"
+    assert bench.code_text(a) == bench.code_text(b)
+    assert bench.code_text(a) != bench.code_text(c)
+    assert "doubles" not in bench.code_text(a) and "twice" not in bench.code_text(a)
