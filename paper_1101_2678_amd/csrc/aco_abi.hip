@@ -185,8 +185,9 @@ hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t b
 // Construction shape per instance size: the tile (cities per lane) and the
 // wavefronts per ant.  Default: 4 cities per lane up to n = 256, 8 above,
 // one wavefront per ant (single-instance construction with m = n on MI355X:
-// tile 4 about 3% faster at n = 64..256, tile 8 about 10% faster at
-// 512..1024).  The table is filled once, on first use, by a function-local
+// tile 4 5-7% faster at n = 64..256, tile 8 7-12% faster at 320..1024, two
+// or four wavefronts per ant 5-30% slower).  The table is filled once, on
+// first use, by a function-local
 // static (thread-safe initialisation); changing it while other threads read
 // it is not supported.
 namespace {
