@@ -187,9 +187,8 @@ hipError_t upload_and_init(const Colony& col, const int32_t* dist_host, size_t b
 // one wavefront per ant (single-instance construction with m = n on MI355X:
 // tile 4 5-7% faster at n = 64..256, tile 8 7-12% faster at 320..1024, two
 // or four wavefronts per ant 5-30% slower).  The table is filled once, on
-// first use, by a function-local
-// static (thread-safe initialisation); changing it while other threads read
-// it is not supported.
+// first use, by a function-local static (thread-safe initialisation);
+// changing it while other threads read it is not supported.
 namespace {
 constexpr int kTile4Max = 256;
 
