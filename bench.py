@@ -600,6 +600,11 @@ def bench_batch(args, torch, aco):
     b.run(iters, graph=True)  # replays it: iterations 25..49
     b.sync()
     t_batch = time.perf_counter() - t0
+    # bytes the batched construction asks for (it skips 4-city groups once all
+    # are visited), estimated from each instance's last tours
+    req_iter = sum(requested_bytes(b.tours(q)[0], int(n), skip=True)
+                   for q, n in enumerate(sizes))
+    choice_footprint = sum(int(n) * ((int(n) + 63) // 64 * 64) * 4 for n in sizes)
     cols = [aco.Colony(d, p["m"], ALPHA, BETA, RHO, p["seed"], atomic=False, stream=stream)
             for d, p in zip(dists, params)]
     for c in cols:
@@ -655,6 +660,18 @@ def bench_batch(args, torch, aco):
         "roofline": job_roofline(
             float(sum(construct_bytes(int(n), int(n)) for n in sizes)) * iters, t_batch, count),
     }
+    rf = rec["roofline"]
+    rf["requested_bytes"] = int(req_iter) * iters
+    rf["requested_GBps"] = round(req_iter * iters / t_batch / 1e9, 1)
+    rf["frac_requested"] = round(rf["requested_GBps"] / HBM_PEAK_GBPS, 4)
+    rf["choice_footprint_bytes"] = choice_footprint
+    rf["frac_note"] = (
+        f"achieved counts every ant-step's whole choice row; the batched kernel asks for "
+        f"{req_iter * iters / rf['algorithmic_bytes']:.3f} of those bytes (it skips 4-city groups "
+        f"once all are visited; estimated from each instance's last tours), and the "
+        f"construction reads only the choice matrices, {choice_footprint / 1e6:.0f} MB "
+        f"together, which the Infinity Cache holds and of which the small instances' sit in "
+        f"L2, so the whole-job rate can pass the HBM figure")
     aco.reset_tiles()
     return rec
 
