@@ -136,6 +136,16 @@ def test_parity_five_and_six_passes(n):
     compare_run(d, 40, 1, 2, 0.5, seed=n + 5, iters=3)
 
 
+@pytest.mark.parametrize("m", [2047, 2048, 3001])
+def test_parity_many_ants(m):
+    """Colonies on each side of the ant count from which both LDS-combining
+    updates sum the deposits to the shared neighbours in registers, over
+    enough iterations for most ants to share them: every tour, length, tau
+    and choice bit-exact, gather and atomic."""
+    _, d = tsp_inputs.instance(60, "cluster", side=100_000, seed=m)
+    compare_run(d, m, 1, 2, 0.5, seed=m + 11, iters=8)
+
+
 @pytest.mark.parametrize("layout", ["uniform", "cluster"])
 def test_parity_n1000_full(layout):
     """The n = m = 1000 workload in full (both layouts, instance seed 1,
